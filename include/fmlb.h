@@ -1,0 +1,250 @@
+/*
+ * fmlb — fluctuating multicomponent lattice Boltzmann on MI355X (gfx950).
+ *
+ * C ABI of the hot path of the two-species fluctuating lattice Boltzmann
+ * equation (FLBE) of Belardinelli, Sbragaglia, Biferale, Gross and Varnik,
+ * "Fluctuating multicomponent lattice Boltzmann model" (arXiv:1410.5584):
+ * one fused stream + collide + noise + mean-field-force step per call site,
+ * on D2Q9 or D3Q19, plus the observables the paper checks it with.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every function returns fmlb_status: 0 on success, a negative code on
+ *    error.  No function aborts or throws; on error nothing is launched and
+ *    the context is unchanged unless stated.  fmlb_status_string() names a code.
+ *  - Device memory is owned by the caller (e.g. PyTorch).  The library
+ *    borrows the buffers passed to fmlb_create(), never frees them, and
+ *    allocates no device memory itself, on the step path or elsewhere.
+ *  - Host pointers are owned by the caller and only read / written during the
+ *    call.
+ *  - One context drives one HIP stream (passed as a hipStream_t cast to
+ *    void*; NULL = the legacy default stream).  Launches are asynchronous on
+ *    that stream unless a function is documented as synchronising.  A context
+ *    is not thread-safe.
+ *  - Lattice sites are indexed s = x + nx * (y + ny * z), x fastest; D2Q9
+ *    lattices have nz = 1.  Periodic boundaries in every direction.
+ *  - Velocity order.  D2Q9: (0,0) (1,0) (0,1) (-1,0) (0,-1) (1,1) (-1,1)
+ *    (-1,-1) (1,-1).  D3Q19: (0,0,0) (1,0,0) (-1,0,0) (0,1,0) (0,-1,0)
+ *    (0,0,1) (0,0,-1) (1,1,0) (-1,-1,0) (1,-1,0) (-1,1,0) (1,0,1) (-1,0,-1)
+ *    (1,0,-1) (-1,0,1) (0,1,1) (0,-1,-1) (0,1,-1) (0,-1,1).
+ *  - Mode order (used by fmlb_mode_variances).  D2Q9: Table I of the paper
+ *    (rho, j_x, j_y, e, P_ww, P_xy, q_x, q_y, epsilon).  D3Q19: the Hermite
+ *    modes of Eq. (26) (1, c_x, c_y, c_z, c_x^2-1/3, c_y^2-1/3, c_z^2-1/3,
+ *    c_x c_y, c_y c_z, c_x c_z) followed by the ghosts (3|c|^2-5) c_alpha,
+ *    (c_y^2-c_z^2) c_x, (c_z^2-c_x^2) c_y, (c_x^2-c_y^2) c_z,
+ *    (2|c|^2-3)(3c_x^2-|c|^2), (2|c|^2-3)(c_y^2-c_z^2), 3|c|^4-6|c|^2+1.
+ *  - Every observable refers to the pre-collision populations f_bar(r, n)
+ *    after n completed steps (Sec. V A, Eq. (63): the stored variables of
+ *    the scheme); the barycentric velocity is the physical one,
+ *    v_b_bar + a_b / 2 (Eq. (70)).
+ *  - Thermal noise uses the counter-based generator Philox4x32-10 (Salmon et
+ *    al., SC'11) keyed by the 64-bit seed, with counter (site, step mod 2^32,
+ *    block, step / 2^32); the four words of block j are words 4j..4j+3 of
+ *    the site's stream, and word w gives the normals 2w, 2w+1 by
+ *    trigonometric Box-Muller from the uniforms u = (2U + 1) / 2^17 of its
+ *    high (radius) and low (angle) 16 bits.  Normal k of a site feeds: k < D
+ *    the momentum noise (+ for species 1, - for species 2, Eq. (74)); then
+ *    the non-momentum modes a = D+1..Q-1 of species 1, then of species 2.
+ *    Results therefore depend only on (seed, site, step), never on launch
+ *    shape or on how many steps one call advances.
+ */
+#ifndef FMLB_H
+#define FMLB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t fmlb_status;
+
+enum {
+    FMLB_OK = 0,
+    FMLB_E_INVALID = -1, /* a parameter is out of range (see fmlb_params)          */
+    FMLB_E_SIZE = -2,    /* a buffer is too small                                   */
+    FMLB_E_HIP = -3,     /* a HIP call failed; fmlb_last_hip_error() has the code   */
+    FMLB_E_STATE = -4,   /* populations not initialised yet                         */
+    FMLB_E_NULL = -5,    /* a required pointer is NULL                              */
+    FMLB_E_UNSUPPORTED = -6 /* the combination is not built (e.g. S(k) on a huge lattice) */
+};
+
+typedef enum { FMLB_D2Q9 = 0, FMLB_D3Q19 = 1 } fmlb_lattice;
+
+/* Storage of the populations in device memory.  The arithmetic is FP64 for
+ * FMLB_F64 and FP32 for every other storage.  The 16-bit forms store the
+ * deviation f_i - w_i rho_ref (rounded to nearest even). */
+typedef enum {
+    FMLB_F64 = 0,
+    FMLB_F32 = 1,
+    FMLB_BF16_DEV = 2,
+    FMLB_F16_DEV = 3
+} fmlb_storage;
+
+enum {
+    FMLB_NOISE_OFF = 1u,    /* deterministic lattice Boltzmann (no thermal noise)            */
+    FMLB_NOISE_NO_SDF = 2u  /* no noise on the momentum modes ("no-sdf", Sec. VI A)          */
+};
+
+/* Parameters of one lattice (all in lattice units, k_B = 1). */
+typedef struct fmlb_params {
+    int32_t lattice;    /* fmlb_lattice                                                    */
+    int32_t storage;    /* fmlb_storage                                                    */
+    int32_t nx, ny, nz; /* >= 1 each; nz == 1 for D2Q9                                     */
+    double tau[2];      /* lambda_bar_sigma = 1/tau_sigma for the transport and ghost modes
+                           of species sigma (Table I, one value per species); tau > 1/2     */
+    double tau_d;       /* lambda_bar_d = 1/tau_d for the momentum modes of both species
+                           (Eq. (37): common, so total momentum is conserved); > 1/2       */
+    double G;           /* coupling of the lattice force, Eq. (87) (G = G')               */
+    double kT;          /* k_B T >= 0; mu = k_B T / c_s^2 with c_s^2 = 1/3 (Eq. (18))      */
+    double rho_ref[2];  /* reference density per species for the 16-bit deviation storage */
+    uint64_t seed;      /* Philox key                                                      */
+    uint32_t flags;     /* FMLB_NOISE_* bits                                               */
+} fmlb_params;
+
+typedef struct fmlb_ctx fmlb_ctx;
+
+/* Buffer indices for fmlb_required_bytes / fmlb_create. */
+enum { FMLB_BUF_POPS_A = 0, FMLB_BUF_POPS_B = 1, FMLB_BUF_SCRATCH = 2 };
+
+/* Bytes the caller must provide for buffer `which` (FMLB_BUF_*), 0 if the
+ * parameters are invalid.  POPS_A / POPS_B: 2 * Q * sites * element size
+ * (the two population arrays of the pull scheme).  SCRATCH: densities,
+ * FP64 staging for host transfers, FP64 structure-factor accumulators and
+ * DFT workspace, reduction partials.  Each buffer must be 256-byte aligned. */
+size_t fmlb_required_bytes(const fmlb_params *p, int which);
+
+/* Validate `p` and bind the three caller-owned device buffers (FMLB_BUF_*
+ * order) and the HIP stream.  Errors: FMLB_E_NULL, FMLB_E_INVALID (tau or
+ * tau_d <= 1/2, kT < 0, a size < 1, D2Q9 with nz != 1, unknown lattice or
+ * storage, more than 2^31 sites), FMLB_E_HIP.  The populations are
+ * uninitialised until fmlb_init_density or fmlb_set_populations. */
+fmlb_status fmlb_create(const fmlb_params *p, void *hip_stream, void *const dev_buf[3],
+                        fmlb_ctx **out);
+
+/* Free the context (not the caller's buffers).  NULL is a no-op. */
+void fmlb_destroy(fmlb_ctx *ctx);
+
+/* Rest state f_bar_i(r, 0) = w_i rho_sigma(r) from host densities
+ * rho1[sites], rho2[sites] (FP64); sets the step counter to 0.  The uniform
+ * rest state is the paper's initial condition (Sec. VI A).  Synchronises. */
+fmlb_status fmlb_init_density(fmlb_ctx *ctx, const double *rho1, const double *rho2);
+
+/* Advance n >= 0 steps of the FLBE update, Eq. (84): per site, pull the
+ * populations streamed from r - c_i, compute rho, j_bar (Eq. (86)), the
+ * lattice force of Eq. (87) from the neighbours' densities of the same step,
+ * the collision R_a of Eq. (85) with the renormalised forcing of Eq. (72)
+ * and the noise of Eq. (74) with the local densities (Sec. IV B), and write
+ * the post-collision populations.  Asynchronous. */
+fmlb_status fmlb_step(fmlb_ctx *ctx, int64_t n);
+
+/* Number of completed steps. */
+int64_t fmlb_current_step(const fmlb_ctx *ctx);
+
+/* rho[2][sites] and j_bar[2][D][sites] (Eq. (86)) of the current state,
+ * FP64, into host memory.  Either pointer may be NULL.  Synchronises. */
+fmlb_status fmlb_moments(fmlb_ctx *ctx, double *rho, double *j);
+
+/* FP64 global sums of the current state: out[0] = sum rho_1,
+ * out[1] = sum rho_2, out[2 + alpha] = sum (j_bar_1 + j_bar_2)_alpha,
+ * alpha < D (mass and total momentum, conserved by the update: R_0 = 0 and
+ * opposite momentum noise, Sec. V A / Eq. (74)).  out has 2 + D entries.
+ * Synchronises. */
+fmlb_status fmlb_global_sums(fmlb_ctx *ctx, double *out);
+
+/* Add the current state's mode statistics to the running sums: for every
+ * species and mode a, sum over sites of m_a and m_a^2 (m_a = sum_i T_ai
+ * f_bar_i, Eq. (80)), in FP64.  Asynchronous. */
+fmlb_status fmlb_mode_accumulate(fmlb_ctx *ctx);
+
+/* out[2][Q] = (<m_a^2> - <m_a>^2) / (N_a mu rho_ref_sigma), the
+ * equipartition ratio of Eq. (50) (1 in equilibrium), from the running sums;
+ * n_samples = number of accumulated snapshots.  Synchronises. */
+fmlb_status fmlb_mode_variances(fmlb_ctx *ctx, double *out, int64_t *n_samples);
+
+/* Structure factors (Sec. VI A): add |X_hat(k)|^2 / sites-type products of
+ * the current state to FP64 accumulators, X_hat(k) = sum_r dX(r) e^{-i k.r},
+ * dX = X - spatial mean, k = 2 pi n / L.  Accumulated quantities (index
+ * `which` of fmlb_sk_get): 0 S_rho1rho1, 1 S_rho2rho2, 2 Re S_rho1rho2,
+ * 3 S_j1j1, 4 S_j2j2, 5 Re S_j1j2 (j_bar, averaged over the D components),
+ * 6 S_vbvb (physical barycentric velocity, averaged over components).
+ * Asynchronous. */
+fmlb_status fmlb_sk_accumulate(fmlb_ctx *ctx);
+
+/* out[sites] (same k layout as the lattice, k_x fastest, FFT order) = the
+ * mean of quantity `which` over the accumulated snapshots; n_samples may be
+ * NULL.  FMLB_E_INVALID for an unknown `which`.  Synchronises. */
+fmlb_status fmlb_sk_get(fmlb_ctx *ctx, int which, double *out, int64_t *n_samples);
+
+/* Clear the structure-factor and mode accumulators.  Asynchronous. */
+fmlb_status fmlb_reset_accumulators(fmlb_ctx *ctx);
+
+/* Pre-collision populations f_bar[2][Q][sites] (FP64, absolute values) to /
+ * from host memory: checkpoint and test I/O.  `bytes` must be at least
+ * 16 * Q * sites.  set_populations also sets the step counter (the noise
+ * of the next step uses counter `step`).  Synchronise. */
+fmlb_status fmlb_get_populations(fmlb_ctx *ctx, double *host, size_t bytes);
+fmlb_status fmlb_set_populations(fmlb_ctx *ctx, const double *host, size_t bytes, int64_t step);
+
+/* Bit-exact checkpoint of the stored state in its device representation
+ * (fmlb_required_bytes(p, FMLB_BUF_POPS_A) bytes) plus the step counter.
+ * Restoring and stepping reproduces an uninterrupted run bit for bit.
+ * Synchronise. */
+fmlb_status fmlb_save_raw(fmlb_ctx *ctx, void *host, size_t bytes, int64_t *step);
+fmlb_status fmlb_load_raw(fmlb_ctx *ctx, const void *host, size_t bytes, int64_t step);
+
+/* counts[0] = sites where not (rho_1 > 0 and rho_2 > 0) (the noise amplitude
+ * of such a site is taken as 0, Sec. VII: local densities), counts[1] =
+ * sites with a non-finite population, for the current state.  Synchronises. */
+fmlb_status fmlb_health(fmlb_ctx *ctx, int64_t counts[2]);
+
+/* Launch shape of the fused step: tile of tile_x x tile_y sites per
+ * workgroup in the plane orthogonal to the march axis (z for D3Q19, y for
+ * D2Q9, where tile_y must be 1) and `march` planes walked per workgroup.
+ * Supported tiles: D3Q19 64x4, 64x8, 32x8, 32x16; D2Q9 64x1, 128x1, 256x1.
+ * 0 = default for each argument.  tile_x = 1 selects the two-pass form (a
+ * density pass, then the step).  Results do not depend on the choice (same
+ * bits).  FMLB_E_INVALID for an unsupported shape. */
+fmlb_status fmlb_set_tile(fmlb_ctx *ctx, int tile_x, int tile_y, int march);
+
+/* Human-readable name of a status code; the last HIP error code of any call. */
+const char *fmlb_status_string(fmlb_status s);
+int32_t fmlb_last_hip_error(void);
+
+/* ------------------------------------------------------------------------ */
+/* Batched replicas: many independent D2Q9 lattices (square or rectangular,  */
+/* FP32 storage) with their own seed, k_BT and G, stepped together by one    */
+/* launch per step over a tile work list covering every replica.  Each       */
+/* replica evolves exactly as it would alone (the noise counter uses the     */
+/* replica's own site index and seed).                                       */
+/* ------------------------------------------------------------------------ */
+typedef struct fmlb_batch fmlb_batch;
+
+/* Bytes of buffer `which` (FMLB_BUF_*) for n replicas described by p[n]
+ * (every p[r] must be D2Q9 with storage FMLB_F32). */
+size_t fmlb_batch_required_bytes(const fmlb_params *p, int n, int which);
+fmlb_status fmlb_batch_create(const fmlb_params *p, int n, void *hip_stream,
+                              void *const dev_buf[3], fmlb_batch **out);
+void fmlb_batch_destroy(fmlb_batch *b);
+/* rho[sites_r] per species, as fmlb_init_density, for replica r. */
+fmlb_status fmlb_batch_init_density(fmlb_batch *b, int r, const double *rho1, const double *rho2);
+/* Advance every replica n steps.  use_graph != 0 replays a captured HIP
+ * graph of the step launch(es) instead of launching eagerly. */
+fmlb_status fmlb_batch_step(fmlb_batch *b, int64_t n, int use_graph);
+fmlb_status fmlb_batch_get_populations(fmlb_batch *b, int r, double *host, size_t bytes);
+fmlb_status fmlb_batch_global_sums(fmlb_batch *b, int r, double *out);
+/* Per-replica equipartition: accumulate, then out[2][9] ratios as
+ * fmlb_mode_variances for replica r (normalised with that replica's k_BT
+ * and rho_ref). */
+fmlb_status fmlb_batch_mode_accumulate(fmlb_batch *b);
+fmlb_status fmlb_batch_mode_variances(fmlb_batch *b, int r, double *out, int64_t *n_samples);
+/* Tile work list shape (tile_x sites per workgroup row, tile_y rows); 0 =
+ * default.  Results do not depend on it. */
+fmlb_status fmlb_batch_set_tile(fmlb_batch *b, int tile_x, int tile_y);
+int64_t fmlb_batch_total_sites(const fmlb_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FMLB_H */

@@ -72,8 +72,14 @@ def lib():
         L.orc_moments.argtypes = [ctypes.c_void_p, dp, dp, dp]
         L.orc_collide_site.argtypes = [ctypes.c_void_p, ctypes.c_int64, dp]
         L.orc_health.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]
+        L.orc_num_threads.restype = ctypes.c_int
+        L.orc_num_threads.argtypes = []
         _lib = L
     return _lib
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
 
 
 def _dp(a: np.ndarray):

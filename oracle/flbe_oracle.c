@@ -21,6 +21,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define QMAX 19
 #define SPECIES 2
@@ -225,31 +228,27 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
     out[3] = x3;
 }
 
-/* Uniform number k of a site and step.  Block j = k / 5 is
- * Philox4x32-10(counter = (site, step mod 2^32, j, step / 2^32),
- * key = (seed mod 2^32, seed / 2^32)); its words x0..x3 give the 23-bit
- * integers U = x_t >> 9 (t = 0..3) and, from the unused low bits,
- * U = (x0 & 0x1ff) | (x1 & 0x1ff) << 9 | (x2 & 0x1f) << 18 (t = 4).
- * The uniform is u = (2U + 1) / 2^24, in (0, 1). */
+/* Uniform number k of a site and step.  Word w = k / 2 of the site's stream
+ * is word w % 4 of block j = w / 4, Philox4x32-10(counter = (site,
+ * step mod 2^32, j, step / 2^32), key = (seed mod 2^32, seed / 2^32)).
+ * Each word gives two 16-bit integers, U = word >> 16 (even k) and
+ * U = word & 0xffff (odd k); the uniform is u = (2U + 1) / 2^17, in (0, 1). */
 void orc_uniforms(uint64_t seed, uint32_t site, int64_t step, int n, double *u)
 {
     const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
     uint32_t x[4] = {0, 0, 0, 0};
     int have = -1;
     for (int k = 0; k < n; ++k) {
-        const int j = k / 5, t = k % 5;
+        const int w = k / 2, j = w / 4;
         if (j != have) {
             const uint32_t ctr[4] = {site, (uint32_t)(uint64_t)step, (uint32_t)j,
                                      (uint32_t)((uint64_t)step >> 32)};
             orc_philox4x32_10(ctr, key, x);
             have = j;
         }
-        uint32_t U;
-        if (t < 4)
-            U = x[t] >> 9;
-        else
-            U = (x[0] & 0x1ffu) | ((x[1] & 0x1ffu) << 9) | ((x[2] & 0x1fu) << 18);
-        u[k] = ldexp(2.0 * (double)U + 1.0, -24);
+        const uint32_t word = x[w % 4];
+        const uint32_t U = (k % 2 == 0) ? (word >> 16) : (word & 0xffffu);
+        u[k] = ldexp(2.0 * (double)U + 1.0, -17);
     }
 }
 
@@ -600,4 +599,13 @@ int orc_health(const orc_sim *cs, int64_t counts[2])
     counts[0] = nonpos;
     counts[1] = nonfinite;
     return 0;
+}
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }

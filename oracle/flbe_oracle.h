@@ -50,8 +50,9 @@ int orc_basis(int lattice, int *D, int *c, double *w, double *T, double *N);
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 
 /* The K Gaussian normals of one site and step (project convention: counter
- * (site, step_lo, block, step_hi), key (seed_lo, seed_hi), five 23-bit
- * uniforms per block, trigonometric Box-Muller on consecutive pairs). */
+ * (site, step_lo, block, step_hi), key (seed_lo, seed_hi), each 32-bit word
+ * split into two 16-bit uniforms, trigonometric Box-Muller on consecutive
+ * pairs, i.e. one word per pair of normals). */
 void orc_uniforms(uint64_t seed, uint32_t site, int64_t step, int n, double *u);
 void orc_normals(uint64_t seed, uint32_t site, int64_t step, int K, double *z);
 
@@ -80,6 +81,9 @@ int orc_collide_site(const orc_sim *s, int64_t site, double *fstar);
 
 /* Sites with rho_sigma <= 0 (either species), sites with a non-finite population. */
 int orc_health(const orc_sim *s, int64_t counts[2]);
+
+/* Threads the OpenMP loops use. */
+int orc_num_threads(void);
 
 #ifdef __cplusplus
 }

@@ -1,0 +1,339 @@
+"""Python binding of the fmlb C ABI (include/fmlb.h).
+
+Argument marshalling only: every function below forwards to the entry point of
+the same name in the in-tree HIP library ``libfmlb.so``; all lattice work runs
+in its kernels.  PyTorch provides device memory and the HIP stream.  There is
+no fallback: if the library has not been built the import of the entry points
+fails with an error that says so.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfmlb.so")
+
+FMLB_OK = 0
+FMLB_E_INVALID = -1
+FMLB_E_SIZE = -2
+FMLB_E_HIP = -3
+FMLB_E_STATE = -4
+FMLB_E_NULL = -5
+FMLB_E_UNSUPPORTED = -6
+
+FMLB_D2Q9, FMLB_D3Q19 = 0, 1
+FMLB_F64, FMLB_F32, FMLB_BF16_DEV, FMLB_F16_DEV = 0, 1, 2, 3
+FMLB_NOISE_OFF, FMLB_NOISE_NO_SDF = 1, 2
+FMLB_BUF_POPS_A, FMLB_BUF_POPS_B, FMLB_BUF_SCRATCH = 0, 1, 2
+
+LATTICES = {"d2q9": FMLB_D2Q9, "d3q19": FMLB_D3Q19}
+STORAGES = {"f64": FMLB_F64, "f32": FMLB_F32, "bf16": FMLB_BF16_DEV, "f16": FMLB_F16_DEV}
+SK_NAMES = ["rho1rho1", "rho2rho2", "rho1rho2", "j1j1", "j2j2", "j1j2", "vbvb"]
+
+
+class fmlb_params(ctypes.Structure):
+    _fields_ = [("lattice", ctypes.c_int32), ("storage", ctypes.c_int32), ("nx", ctypes.c_int32),
+                ("ny", ctypes.c_int32), ("nz", ctypes.c_int32), ("tau", ctypes.c_double * 2),
+                ("tau_d", ctypes.c_double), ("G", ctypes.c_double), ("kT", ctypes.c_double),
+                ("rho_ref", ctypes.c_double * 2), ("seed", ctypes.c_uint64), ("flags", ctypes.c_uint32)]
+
+
+class FmlbError(RuntimeError):
+    def __init__(self, fn: str, status: int):
+        msg = lib().fmlb_status_string(status).decode()
+        extra = f" (hip error {lib().fmlb_last_hip_error()})" if status == FMLB_E_HIP else ""
+        super().__init__(f"{fn}: {msg}{extra} [status {status}]")
+        self.status = status
+
+
+_lib = None
+
+_vp = ctypes.c_void_p
+_dp = ctypes.POINTER(ctypes.c_double)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_pp = ctypes.POINTER(fmlb_params)
+
+_SIGNATURES = {
+    "fmlb_required_bytes": (ctypes.c_size_t, [_pp, ctypes.c_int]),
+    "fmlb_create": (ctypes.c_int32, [_pp, _vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp)]),
+    "fmlb_destroy": (None, [_vp]),
+    "fmlb_init_density": (ctypes.c_int32, [_vp, _dp, _dp]),
+    "fmlb_step": (ctypes.c_int32, [_vp, ctypes.c_int64]),
+    "fmlb_current_step": (ctypes.c_int64, [_vp]),
+    "fmlb_moments": (ctypes.c_int32, [_vp, _dp, _dp]),
+    "fmlb_global_sums": (ctypes.c_int32, [_vp, _dp]),
+    "fmlb_mode_accumulate": (ctypes.c_int32, [_vp]),
+    "fmlb_mode_variances": (ctypes.c_int32, [_vp, _dp, _i64p]),
+    "fmlb_sk_accumulate": (ctypes.c_int32, [_vp]),
+    "fmlb_sk_get": (ctypes.c_int32, [_vp, ctypes.c_int, _dp, _i64p]),
+    "fmlb_reset_accumulators": (ctypes.c_int32, [_vp]),
+    "fmlb_get_populations": (ctypes.c_int32, [_vp, _dp, ctypes.c_size_t]),
+    "fmlb_set_populations": (ctypes.c_int32, [_vp, _dp, ctypes.c_size_t, ctypes.c_int64]),
+    "fmlb_save_raw": (ctypes.c_int32, [_vp, _vp, ctypes.c_size_t, _i64p]),
+    "fmlb_load_raw": (ctypes.c_int32, [_vp, _vp, ctypes.c_size_t, ctypes.c_int64]),
+    "fmlb_health": (ctypes.c_int32, [_vp, _i64p]),
+    "fmlb_set_tile": (ctypes.c_int32, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "fmlb_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
+    "fmlb_last_hip_error": (ctypes.c_int32, []),
+    "fmlb_batch_required_bytes": (ctypes.c_size_t, [_pp, ctypes.c_int, ctypes.c_int]),
+    "fmlb_batch_create": (ctypes.c_int32, [_pp, ctypes.c_int, _vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp)]),
+    "fmlb_batch_destroy": (None, [_vp]),
+    "fmlb_batch_init_density": (ctypes.c_int32, [_vp, ctypes.c_int, _dp, _dp]),
+    "fmlb_batch_step": (ctypes.c_int32, [_vp, ctypes.c_int64, ctypes.c_int]),
+    "fmlb_batch_get_populations": (ctypes.c_int32, [_vp, ctypes.c_int, _dp, ctypes.c_size_t]),
+    "fmlb_batch_global_sums": (ctypes.c_int32, [_vp, ctypes.c_int, _dp]),
+    "fmlb_batch_mode_accumulate": (ctypes.c_int32, [_vp]),
+    "fmlb_batch_mode_variances": (ctypes.c_int32, [_vp, ctypes.c_int, _dp, _i64p]),
+    "fmlb_batch_set_tile": (ctypes.c_int32, [_vp, ctypes.c_int, ctypes.c_int]),
+    "fmlb_batch_total_sites": (ctypes.c_int64, [_vp]),
+}
+
+
+def lib():
+    """The loaded HIP library.  Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library {LIB_PATH} is missing: build it first "
+                               "(python -c 'import __graft_entry__ as g; g.build()')")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(fn: str, status: int):
+    if status != FMLB_OK:
+        raise FmlbError(fn, status)
+
+
+def _f64(a) -> np.ndarray:
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(_dp)
+
+
+# ---- entry points with the C names (marshalling only) ------------------------
+
+def fmlb_required_bytes(p: fmlb_params, which: int) -> int:
+    return lib().fmlb_required_bytes(ctypes.byref(p), which)
+
+
+def fmlb_create(p: fmlb_params, stream: int, bufs) -> int:
+    arr = (_vp * 3)(*[_vp(int(b)) for b in bufs])
+    out = _vp()
+    _check("fmlb_create", lib().fmlb_create(ctypes.byref(p), _vp(stream), arr, ctypes.byref(out)))
+    return out.value
+
+
+def fmlb_destroy(ctx: int):
+    lib().fmlb_destroy(_vp(ctx))
+
+
+def fmlb_init_density(ctx: int, rho1: np.ndarray, rho2: np.ndarray):
+    r1, r2 = _f64(rho1), _f64(rho2)
+    _check("fmlb_init_density", lib().fmlb_init_density(_vp(ctx), _ptr(r1), _ptr(r2)))
+
+
+def fmlb_step(ctx: int, n: int):
+    _check("fmlb_step", lib().fmlb_step(_vp(ctx), int(n)))
+
+
+def fmlb_current_step(ctx: int) -> int:
+    return lib().fmlb_current_step(_vp(ctx))
+
+
+def fmlb_moments(ctx: int, rho: np.ndarray | None, j: np.ndarray | None):
+    _check("fmlb_moments", lib().fmlb_moments(_vp(ctx), _ptr(rho) if rho is not None else None,
+                                              _ptr(j) if j is not None else None))
+
+
+def fmlb_global_sums(ctx: int, out: np.ndarray):
+    _check("fmlb_global_sums", lib().fmlb_global_sums(_vp(ctx), _ptr(out)))
+
+
+def fmlb_mode_accumulate(ctx: int):
+    _check("fmlb_mode_accumulate", lib().fmlb_mode_accumulate(_vp(ctx)))
+
+
+def fmlb_mode_variances(ctx: int, out: np.ndarray) -> int:
+    n = ctypes.c_int64()
+    _check("fmlb_mode_variances", lib().fmlb_mode_variances(_vp(ctx), _ptr(out), ctypes.byref(n)))
+    return n.value
+
+
+def fmlb_sk_accumulate(ctx: int):
+    _check("fmlb_sk_accumulate", lib().fmlb_sk_accumulate(_vp(ctx)))
+
+
+def fmlb_sk_get(ctx: int, which: int, out: np.ndarray) -> int:
+    n = ctypes.c_int64()
+    _check("fmlb_sk_get", lib().fmlb_sk_get(_vp(ctx), which, _ptr(out), ctypes.byref(n)))
+    return n.value
+
+
+def fmlb_reset_accumulators(ctx: int):
+    _check("fmlb_reset_accumulators", lib().fmlb_reset_accumulators(_vp(ctx)))
+
+
+def fmlb_get_populations(ctx: int, out: np.ndarray):
+    _check("fmlb_get_populations", lib().fmlb_get_populations(_vp(ctx), _ptr(out), out.nbytes))
+
+
+def fmlb_set_populations(ctx: int, f: np.ndarray, step: int):
+    f = _f64(f)
+    _check("fmlb_set_populations", lib().fmlb_set_populations(_vp(ctx), _ptr(f), f.nbytes, int(step)))
+
+
+def fmlb_save_raw(ctx: int, out: np.ndarray) -> int:
+    step = ctypes.c_int64()
+    _check("fmlb_save_raw", lib().fmlb_save_raw(_vp(ctx), _vp(out.ctypes.data), out.nbytes, ctypes.byref(step)))
+    return step.value
+
+
+def fmlb_load_raw(ctx: int, raw: np.ndarray, step: int):
+    raw = np.ascontiguousarray(raw)
+    _check("fmlb_load_raw", lib().fmlb_load_raw(_vp(ctx), _vp(raw.ctypes.data), raw.nbytes, int(step)))
+
+
+def fmlb_health(ctx: int):
+    c = (ctypes.c_int64 * 2)()
+    _check("fmlb_health", lib().fmlb_health(_vp(ctx), c))
+    return int(c[0]), int(c[1])
+
+
+def fmlb_set_tile(ctx: int, tile_x: int, tile_y: int, march: int):
+    _check("fmlb_set_tile", lib().fmlb_set_tile(_vp(ctx), tile_x, tile_y, march))
+
+
+# ---- convenience wrapper: torch-owned buffers, numpy host arrays ------------
+
+@dataclass
+class Params:
+    lattice: str = "d2q9"
+    storage: str = "f64"
+    nx: int = 64
+    ny: int = 64
+    nz: int = 1
+    tau: tuple = (1.0, 1.0)
+    tau_d: float = 1.0
+    G: float = 0.0
+    kT: float = 0.0
+    rho_ref: tuple = (1.0, 1.0)
+    seed: int = 1
+    flags: int = 0
+
+    def c(self) -> fmlb_params:
+        return fmlb_params(LATTICES[self.lattice], STORAGES[self.storage], self.nx, self.ny, self.nz,
+                           (ctypes.c_double * 2)(*self.tau), self.tau_d, self.G, self.kT,
+                           (ctypes.c_double * 2)(*self.rho_ref), self.seed, self.flags)
+
+
+class Lattice:
+    """One lattice on the current CUDA/HIP device.  Device buffers are torch
+    uint8 tensors owned by this object; the stream is torch's current stream
+    at construction."""
+
+    def __init__(self, p: Params, device=None, stream=None):
+        import torch
+        self.p = p
+        cp = p.c()
+        sizes = [fmlb_required_bytes(cp, k) for k in range(3)]
+        if min(sizes) == 0:
+            raise FmlbError("fmlb_required_bytes", FMLB_E_INVALID)
+        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.bufs = [torch.empty(s, dtype=torch.uint8, device=dev) for s in sizes]
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        self.ctx = fmlb_create(cp, self.stream.cuda_stream, [b.data_ptr() for b in self.bufs])
+        self.Q = 9 if p.lattice == "d2q9" else 19
+        self.D = 2 if p.lattice == "d2q9" else 3
+        self.shape = (p.nz, p.ny, p.nx)
+        self.nsites = p.nx * p.ny * p.nz
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            fmlb_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        self.close()
+
+    @property
+    def step_count(self) -> int:
+        return fmlb_current_step(self.ctx)
+
+    def init_density(self, rho1, rho2):
+        r1 = np.broadcast_to(np.asarray(rho1, dtype=np.float64), self.shape)
+        r2 = np.broadcast_to(np.asarray(rho2, dtype=np.float64), self.shape)
+        fmlb_init_density(self.ctx, r1, r2)
+
+    def step(self, n: int = 1):
+        fmlb_step(self.ctx, n)
+
+    def moments(self):
+        rho = np.empty((2,) + self.shape)
+        j = np.empty((2, self.D) + self.shape)
+        fmlb_moments(self.ctx, rho, j)
+        return rho, j
+
+    def global_sums(self):
+        out = np.empty(2 + self.D)
+        fmlb_global_sums(self.ctx, out)
+        return out
+
+    def populations(self):
+        out = np.empty((2, self.Q) + self.shape)
+        fmlb_get_populations(self.ctx, out)
+        return out
+
+    def set_populations(self, f, step: int = 0):
+        fmlb_set_populations(self.ctx, np.asarray(f, dtype=np.float64).reshape(2, self.Q, *self.shape), step)
+
+    def mode_accumulate(self):
+        fmlb_mode_accumulate(self.ctx)
+
+    def mode_variances(self):
+        out = np.empty((2, self.Q))
+        n = fmlb_mode_variances(self.ctx, out)
+        return out, n
+
+    def sk_accumulate(self):
+        fmlb_sk_accumulate(self.ctx)
+
+    def sk(self, which):
+        if isinstance(which, str):
+            which = SK_NAMES.index(which)
+        out = np.empty(self.shape)
+        n = fmlb_sk_get(self.ctx, which, out)
+        return out, n
+
+    def reset_accumulators(self):
+        fmlb_reset_accumulators(self.ctx)
+
+    def save_raw(self):
+        elem = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}[self.p.storage]
+        out = np.empty(2 * self.Q * self.nsites * elem, dtype=np.uint8)
+        step = fmlb_save_raw(self.ctx, out)
+        return out, step
+
+    def load_raw(self, raw, step: int):
+        fmlb_load_raw(self.ctx, raw, step)
+
+    def health(self):
+        return fmlb_health(self.ctx)
+
+    def set_tile(self, tile_x: int = 0, tile_y: int = 0, march: int = 0):
+        fmlb_set_tile(self.ctx, tile_x, tile_y, march)
+
+    def synchronize(self):
+        self.stream.synchronize()

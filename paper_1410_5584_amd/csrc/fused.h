@@ -1,0 +1,373 @@
+// Fused single-pass FLBE step: pull-stream + moments + lattice force + noise
+// + collision + store, one read and one write of every population.
+//
+// The lattice force of Eq. (87) needs the densities of the same time level at
+// the neighbours r + c_i, and those depend on the neighbours' own pulled
+// populations.  Each workgroup therefore owns a tile of T0 x T1 columns of the
+// plane orthogonal to the march axis (z for D3Q19, y for D2Q9) and walks a
+// chunk of planes.  For plane m+1 it pulls the populations of its tile (kept
+// in registers, with their moments, for the next iteration) and of a one-site
+// halo ring around the tile (densities only), and writes both densities into
+// a 4-slot LDS ring of planes; after one barrier it collides plane m with the
+// densities of planes m-1, m, m+1.  Four slots make one barrier per plane
+// sufficient: the slot written for plane m+1 was last read while plane m-2
+// was collided.
+//
+// The densities are produced by the same moments() and the force by the same
+// lattice_acceleration() as the two-pass form, so both forms give the same
+// bits.  The halo recomputation costs extra (mostly L2-resident) loads, not
+// HBM traffic: every population is still fetched from HBM about once.
+//
+// Memory is addressed through one buffer resource per species and array
+// (32-bit per-lane offsets, uniform per-population offsets), which keeps the
+// address arithmetic off the vector ALU.  The fused form is used when a
+// species' array fits in 4 GiB; larger lattices run the two-pass form.
+//
+// Workgroups are numbered so that the 8 XCDs (which take workgroups round
+// robin) each receive a contiguous range of tiles; neighbouring tiles then
+// share one L2 and the halo loads hit it.
+#pragma once
+
+#include <type_traits>
+
+#include "kernels.h"
+
+namespace fmlb {
+
+// Raw buffer access per storage type (values are bit patterns on the wire).
+constexpr int kBufferWord3 = 0x00020000;
+
+template <class S>
+struct BufIO;
+
+template <>
+struct BufIO<float> {
+    __device__ static float load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+    {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+    }
+    __device__ static void store(float v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+    {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, 0);
+    }
+};
+
+template <>
+struct BufIO<__hip_bfloat16> {
+    __device__ static float load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+    {
+        const unsigned short b = __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0);
+        return __builtin_bit_cast(float, (uint32_t)b << 16);
+    }
+    __device__ static void store(float v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+    {
+        const __hip_bfloat16 h = __float2bfloat16(v);
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, h), r, voff, soff, 0);
+    }
+};
+
+template <>
+struct BufIO<__half> {
+    __device__ static float load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+    {
+        const unsigned short b = __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0);
+        return __half2float(__ushort_as_half(b));
+    }
+    __device__ static void store(float v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+    {
+        __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(__float2half_rn(v)), r, voff, soff, 0);
+    }
+};
+
+template <class L>
+struct MarchAxes {
+    static constexpr bool three_d = L::D == 3;
+    // velocity components along plane axis 0 (x), plane axis 1 (y, 3D only)
+    // and the march axis (z in 3D, y in 2D)
+    static constexpr int c0(int i) { return L::cx[i]; }
+    static constexpr int c1(int i) { return three_d ? L::cy[i] : 0; }
+    static constexpr int cm(int i) { return three_d ? L::cz[i] : L::cy[i]; }
+};
+
+template <class L, class S, int T0, int T1, bool STAGE = false>
+__global__ __launch_bounds__(T0 *T1) void fused_step_kernel(StepArgs<L, S> a, int chunk)
+{
+    using Real = typename Storage<S>::Real;
+    using A = MarchAxes<L>;
+    constexpr int Q = L::Q;
+    constexpr bool D3 = A::three_d;
+    constexpr int H0 = T0 + 2;
+    constexpr int H1 = D3 ? T1 + 2 : 1;
+    constexpr int OFF1 = D3 ? 1 : 0;
+    constexpr int PLANE = H0 * H1;
+    constexpr int NT = T0 * T1;
+    constexpr int NHALO = PLANE - NT;
+    constexpr uint32_t ES = sizeof(S);
+    static_assert(D3 || T1 == 1, "2D tiles are one row");
+    static_assert(NHALO <= NT, "halo ring larger than the tile");
+
+    __shared__ Real ring[4][2][PLANE];
+    // STAGE: the next plane's own populations wait in LDS (one private column
+    // per thread) instead of registers during the collision.
+    __shared__ Real pbuf[STAGE ? 2 * Q : 1][STAGE ? NT : 1];
+
+    const Geom g = a.g;
+    const int n0 = g.nx, n1 = D3 ? g.ny : 1, nm = D3 ? g.nz : g.ny;
+    const uint32_t s1 = (uint32_t)n0;                          // site stride along plane axis 1
+    const uint32_t sm = D3 ? (uint32_t)n0 * n1 : (uint32_t)n0;  // site stride along the march axis
+    const uint32_t pop_bytes = (uint32_t)g.nsites * ES;         // one population array
+
+    __amdgpu_buffer_rsrc_t rsrc[2], rdst[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        rsrc[s] = __builtin_amdgcn_make_buffer_rsrc((void *)(a.src + (size_t)s * Q * g.nsites), 0,
+                                                    (int)(Q * pop_bytes), kBufferWord3);
+        rdst[s] = __builtin_amdgcn_make_buffer_rsrc((void *)(a.dst + (size_t)s * Q * g.nsites), 0,
+                                                    (int)(Q * pop_bytes), kBufferWord3);
+    }
+
+    // Tile and chunk of this workgroup; XCD-contiguous numbering.
+    const int tiles0 = (n0 + T0 - 1) / T0, tiles1 = (n1 + T1 - 1) / T1;
+    const int chunks = (nm + chunk - 1) / chunk;
+    const unsigned nblk = (unsigned)tiles0 * tiles1 * chunks;
+    const unsigned b = blockIdx.x;
+    const unsigned per_xcd = (nblk + 7) / 8;
+    const unsigned xcd = b % 8, k = b / 8;
+    const unsigned full = nblk % 8 == 0 ? 8 : nblk % 8;  // XCDs that get per_xcd blocks
+    const unsigned logical = xcd < full ? xcd * per_xcd + k : full * per_xcd + (xcd - full) * (per_xcd - 1) + k;
+    const int t0 = (int)(logical % tiles0);
+    const int t1 = (int)((logical / tiles0) % tiles1);
+    const int ck = (int)(logical / ((unsigned)tiles0 * tiles1));
+    const int mbeg = ck * chunk;
+    const int mend = min(mbeg + chunk, nm);
+
+    const int tid = threadIdx.x;
+    const int l0 = tid % T0, l1 = tid / T0;
+    const int p0raw = t0 * T0 + l0, p1raw = t1 * T1 + l1;
+    const bool inside = p0raw < n0 && p1raw < n1;
+    const int p0 = p0raw % n0, p1 = p1raw % n1;  // periodic image for ragged tiles
+    const int box_own = (l1 + OFF1) * H0 + (l0 + 1);
+
+    // Halo ring position of this thread (tid < NHALO): border of the H0 x H1 box.
+    int hb = -1, hp0 = 0, hp1 = 0;
+    if (tid < NHALO) {
+        int h0, h1;
+        if (!D3) {
+            h0 = tid == 0 ? 0 : H0 - 1;
+            h1 = 0;
+        } else if (tid < H0) {
+            h0 = tid;
+            h1 = 0;
+        } else if (tid < 2 * H0) {
+            h0 = tid - H0;
+            h1 = H1 - 1;
+        } else {
+            const int q = tid - 2 * H0;
+            h0 = (q & 1) ? H0 - 1 : 0;
+            h1 = 1 + (q >> 1);
+        }
+        hb = h1 * H0 + h0;
+        hp0 = ((t0 * T0 - 1 + h0) % n0 + n0) % n0;
+        hp1 = D3 ? ((t1 * T1 - OFF1 + h1) % n1 + n1) % n1 : 0;
+    }
+
+    const Real ref[2] = {a.ref[0], a.ref[1]};
+    auto slot = [&](int m) { return (m - mbeg + 1) & 3; };
+
+    // Pull the 2Q populations of plane-site (q0, q1) on plane m (m wrapped).
+    auto pull = [&](int q0, int q1, int m, Real (&f)[2][Q]) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int x = wrap(q0, -A::c0(i), n0);
+            const int y = D3 ? wrap(q1, -A::c1(i), n1) : 0;
+            const int z = wrap(m, -A::cm(i), nm);
+            const uint32_t voff = ((uint32_t)x + s1 * (uint32_t)y + sm * (uint32_t)z) * ES;
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                Real v = BufIO<S>::load(rsrc[s], voff, (uint32_t)i * pop_bytes);
+                if (Storage<S>::deviation) v += Real(L::w36[i]) / Real(36) * ref[s];
+                f[s][i] = v;
+            }
+        }
+    };
+    auto wrapm = [&](int m) { return m < 0 ? m + nm : (m >= nm ? m - nm : m); };
+
+    Real cur[2][Q], rc[2], jc[2][3];
+    // Prologue: densities of plane mbeg-1, populations and moments of plane mbeg.
+#pragma unroll 1
+    for (int m = mbeg - 1; m <= mbeg; ++m) {
+        Real r, j[3];
+        if (hb >= 0) {
+            Real h[2][Q];
+            pull(hp0, hp1, wrapm(m), h);
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                moments<L, Real>(h[s], r, j);
+                ring[slot(m)][s][hb] = r;
+            }
+        }
+        Real f[2][Q];
+        pull(p0, p1, wrapm(m), f);
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            moments<L, Real>(f[s], r, j);
+            ring[slot(m)][s][box_own] = r;
+            if (m == mbeg) {
+                rc[s] = r;
+#pragma unroll
+                for (int al = 0; al < 3; ++al) jc[s][al] = j[al];
+#pragma unroll
+                for (int i = 0; i < Q; ++i) {
+                    if constexpr (STAGE)
+                        pbuf[s * Q + i][tid] = f[s][i];
+                    else
+                        cur[s][i] = f[s][i];
+                }
+            }
+        }
+    }
+
+#pragma unroll 1
+    for (int m = mbeg; m < mend; ++m) {
+        // Plane m+1: halo densities, then own populations and moments (kept).
+        const int mn = wrapm(m + 1);
+        if (hb >= 0) {
+            Real h[2][Q];
+            pull(hp0, hp1, mn, h);
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                Real r, j[3];
+                moments<L, Real>(h[s], r, j);
+                ring[slot(m + 1)][s][hb] = r;
+            }
+        }
+        Real nxt[2][Q], rn[2], jn[2][3];
+        pull(p0, p1, mn, nxt);
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            moments<L, Real>(nxt[s], rn[s], jn[s]);
+            ring[slot(m + 1)][s][box_own] = rn[s];
+        }
+        if constexpr (STAGE) {
+            // swap through the thread's private LDS column: plane m out, m+1 in
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+#pragma unroll
+                for (int i = 0; i < Q; ++i) {
+                    cur[s][i] = pbuf[s * Q + i][tid];
+                    pbuf[s * Q + i][tid] = nxt[s][i];
+                }
+        }
+        __syncthreads();
+
+        if (inside) {
+            auto nb = [&](int i, int s) -> Real {
+                const int sl = slot(m + A::cm(i));
+                return ring[sl][s][box_own + A::c1(i) * H0 + A::c0(i)];
+            };
+            Real acc[2][3];
+            lattice_acceleration<L, Real>(nb, a.ph.negG, acc);
+            const uint32_t site = (uint32_t)p0 + s1 * (uint32_t)(D3 ? p1 : 0) + sm * (uint32_t)m;
+            const uint32_t voff = site * ES;
+            collide_site<L, Real>(cur, rc, jc, acc, a.ph, Counter{site, a.step_lo, a.step_hi},
+                                  [&](int s, auto &fs) {
+#pragma unroll
+                                      for (int i = 0; i < Q; ++i) {
+                                          Real v = fs[i];
+                                          if (Storage<S>::deviation) v -= Real(L::w36[i]) / Real(36) * ref[s];
+                                          BufIO<S>::store(v, rdst[s], voff, (uint32_t)i * pop_bytes);
+                                      }
+                                  });
+        }
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            rc[s] = rn[s];
+#pragma unroll
+            for (int al = 0; al < 3; ++al) jc[s][al] = jn[s][al];
+            if constexpr (!STAGE) {
+#pragma unroll
+                for (int i = 0; i < Q; ++i) cur[s][i] = nxt[s][i];
+            }
+        }
+    }
+}
+
+// Supported tile shapes (T0 x T1 threads, chunk = planes per workgroup).
+// The fused form is built for the FP32-arithmetic storages only; FP64 storage
+// (the parity configuration) runs the two-pass form, where the FP64 collision
+// fits the register file without spilling.
+template <class L, class S>
+bool fused_shape_valid(int tile_x, int tile_y, int march)
+{
+    if (std::is_same<S, double>::value) return false;
+    if (march < 0 || march > 4096) return false;
+    if (L::D == 3)
+        return (tile_x == 64 && (tile_y == 4 || tile_y == 8)) || (tile_x == 32 && (tile_y == 8 || tile_y == 16));
+    return tile_y == 1 && (tile_x == 64 || tile_x == 128 || tile_x == 256);
+}
+
+template <class L, class S>
+void default_fused_shape(const Geom &g, int &tx, int &ty, int &chunk)
+{
+    if (L::D == 3) {
+        tx = 64;
+        ty = 8;
+        chunk = 64;
+    } else {
+        tx = g.nx >= 256 ? 256 : (g.nx >= 128 ? 128 : 64);
+        ty = 1;
+        chunk = 16;
+    }
+}
+
+template <class L, class S>
+bool fused_supported(const Geom &g, int tile_x, int tile_y, int march)
+{
+    if (std::is_same<S, double>::value) return false;
+    // one species' array must be addressable by a 32-bit buffer offset
+    if ((double)L::Q * (double)g.nsites * (double)sizeof(S) >= 4294967295.0) return false;
+    // Any lattice size otherwise: ragged tiles are masked and every plane
+    // index wraps periodically (with fewer than 3 planes the ring simply holds
+    // copies).
+    return tile_x == 0 || fused_shape_valid<L, S>(tile_x, tile_y, march);
+}
+
+template <class L, class S, int T0, int T1, bool STAGE = false>
+hipError_t launch_fused_shape(const StepArgs<L, S> &a, int chunk, hipStream_t stream)
+{
+    const int n0 = a.g.nx, n1 = L::D == 3 ? a.g.ny : 1, nm = L::D == 3 ? a.g.nz : a.g.ny;
+    const unsigned nblk = (unsigned)((n0 + T0 - 1) / T0) * (unsigned)((n1 + T1 - 1) / T1) *
+                          (unsigned)((nm + chunk - 1) / chunk);
+    hipLaunchKernelGGL((fused_step_kernel<L, S, T0, T1, STAGE>), dim3(nblk), dim3(T0 * T1), 0, stream, a, chunk);
+    return hipGetLastError();
+}
+
+template <class L, class S>
+hipError_t launch_fused(const StepArgs<L, S> &a, int tile_x, int tile_y, int march, hipStream_t stream)
+{
+    if constexpr (std::is_same<S, double>::value) {
+        return hipErrorNotSupported;
+    } else {
+        int tx = tile_x, ty = tile_y, chunk = march;
+        int dtx, dty, dch;
+        default_fused_shape<L, S>(a.g, dtx, dty, dch);
+        if (tx == 0) {
+            tx = dtx;
+            ty = dty;
+        }
+        if (chunk == 0) chunk = dch;
+        if constexpr (L::D == 3) {
+            if (tx == 64 && ty == 4) return launch_fused_shape<L, S, 64, 4>(a, chunk, stream);
+            if (tx == 64 && ty == 8) return launch_fused_shape<L, S, 64, 8>(a, chunk, stream);
+            if (tx == 32 && ty == 8) return launch_fused_shape<L, S, 32, 8>(a, chunk, stream);
+            if (tx == 32 && ty == 16) return launch_fused_shape<L, S, 32, 16>(a, chunk, stream);
+        } else {
+            if (tx == 64) return launch_fused_shape<L, S, 64, 1>(a, chunk, stream);
+            if (tx == 128) return launch_fused_shape<L, S, 128, 1>(a, chunk, stream);
+            if (tx == 256) return launch_fused_shape<L, S, 256, 1>(a, chunk, stream);
+        }
+        return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace fmlb

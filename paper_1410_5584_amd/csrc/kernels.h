@@ -1,0 +1,178 @@
+// Step kernels of the FLBE hot path and the state-transfer kernels.
+//
+// Two step forms share the per-site collision of collide.h and give the same
+// bits:
+//  - density_kernel + step_kernel: the density pass writes rho_sigma(r) of the
+//    pre-collision state (Eq. (86)); the step kernel pulls the populations,
+//    reads the neighbours' densities for the force of Eq. (87), collides and
+//    stores.  Simple, any lattice size.
+//  - fused_step_kernel (fused.h): one pass; each workgroup recomputes the
+//    densities of its tile plus a one-site halo into LDS while marching
+//    through planes.
+#pragma once
+
+#include "collide.h"
+#include "storage.h"
+
+namespace fmlb {
+
+template <class L, class S>
+struct StepArgs {
+    using Real = typename Storage<S>::Real;
+    const S *src;
+    S *dst;
+    Real *rho;  // [2][sites] densities of the pre-collision state (two-pass form)
+    Geom g;
+    Phys<Real> ph;
+    Real ref[2];  // rho_ref per species (deviation storage)
+    uint32_t step_lo, step_hi;
+};
+
+template <class L, class S>
+__device__ __forceinline__ typename Storage<S>::Real load_pop(const S *buf, size_t nsites, int s, int i,
+                                                              size_t site, typename Storage<S>::Real ref)
+{
+    using Real = typename Storage<S>::Real;
+    Real v = Storage<S>::load(buf, ((size_t)(s * L::Q + i)) * nsites + site);
+    if (Storage<S>::deviation) v += Real(L::w36[i]) / Real(36) * ref;
+    return v;
+}
+
+template <class L, class S>
+__device__ __forceinline__ void store_pop(S *buf, size_t nsites, int s, int i, size_t site,
+                                          typename Storage<S>::Real v, typename Storage<S>::Real ref)
+{
+    using Real = typename Storage<S>::Real;
+    if (Storage<S>::deviation) v -= Real(L::w36[i]) / Real(36) * ref;
+    Storage<S>::store(buf, ((size_t)(s * L::Q + i)) * nsites + site, v);
+}
+
+// Pull the 2Q pre-collision populations of site (x, y, z).
+template <class L, class S>
+__device__ __forceinline__ void pull_site(const S *src, const Geom &g, int x, int y, int z,
+                                          const typename Storage<S>::Real (&ref)[2],
+                                          typename Storage<S>::Real (&f)[2][L::Q])
+{
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        const int xs = wrap(x, -L::cx[i], g.nx);
+        const int ys = wrap(y, -L::cy[i], g.ny);
+        const int zs = L::D == 3 ? wrap(z, -L::cz[i], g.nz) : 0;
+        const size_t site = (size_t)xs + (size_t)g.nx * ((size_t)ys + (size_t)g.ny * (size_t)zs);
+#pragma unroll
+        for (int s = 0; s < 2; ++s) f[s][i] = load_pop<L, S>(src, g.nsites, s, i, site, ref[s]);
+    }
+}
+
+template <class L, class S>
+__global__ __launch_bounds__(256) void density_kernel(StepArgs<L, S> a)
+{
+    using Real = typename Storage<S>::Real;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y, z = blockIdx.z;
+    if (x >= a.g.nx) return;
+    Real f[2][L::Q];
+    pull_site<L, S>(a.src, a.g, x, y, z, a.ref, f);
+    const size_t site = (size_t)x + (size_t)a.g.nx * ((size_t)y + (size_t)a.g.ny * (size_t)z);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        Real r, j[3];
+        moments<L, Real>(f[s], r, j);
+        a.rho[(size_t)s * a.g.nsites + site] = r;
+    }
+}
+
+template <class L, class S>
+__global__ __launch_bounds__(256) void step_kernel(StepArgs<L, S> a)
+{
+    using Real = typename Storage<S>::Real;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y, z = blockIdx.z;
+    if (x >= a.g.nx) return;
+    const Geom g = a.g;
+    Real f[2][L::Q];
+    pull_site<L, S>(a.src, g, x, y, z, a.ref, f);
+    const Real *rho = a.rho;
+    auto nb = [&](int i, int s) -> Real {
+        const int xn = wrap(x, L::cx[i], g.nx);
+        const int yn = wrap(y, L::cy[i], g.ny);
+        const int zn = L::D == 3 ? wrap(z, L::cz[i], g.nz) : 0;
+        return rho[(size_t)s * g.nsites + (size_t)xn + (size_t)g.nx * ((size_t)yn + (size_t)g.ny * (size_t)zn)];
+    };
+    Real acc[2][3];
+    lattice_acceleration<L, Real>(nb, a.ph.negG, acc);
+    const size_t site = (size_t)x + (size_t)g.nx * ((size_t)y + (size_t)g.ny * (size_t)z);
+    Real rho_s[2], j_s[2][3];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) moments<L, Real>(f[s], rho_s[s], j_s[s]);
+    collide_site<L, Real>(f, rho_s, j_s, acc, a.ph, Counter{(uint32_t)site, a.step_lo, a.step_hi},
+                          [&](int s, auto &fs) {
+#pragma unroll
+                              for (int i = 0; i < L::Q; ++i)
+                                  store_pop<L, S>(a.dst, g.nsites, s, i, site, fs[i], a.ref[s]);
+                          });
+}
+
+// Rest state from FP64 densities rho[2][sites]: buf_i(r) = w_i rho(r + c_i),
+// i.e. f_bar_i(r, 0) = w_i rho(r) in the pull layout.
+template <class L, class S>
+__global__ __launch_bounds__(256) void init_kernel(S *dst, const double *rho, Geom g,
+                                                   typename Storage<S>::Real ref0,
+                                                   typename Storage<S>::Real ref1)
+{
+    using Real = typename Storage<S>::Real;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y, z = blockIdx.z;
+    if (x >= g.nx) return;
+    const size_t site = (size_t)x + (size_t)g.nx * ((size_t)y + (size_t)g.ny * (size_t)z);
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        const int xn = wrap(x, L::cx[i], g.nx);
+        const int yn = wrap(y, L::cy[i], g.ny);
+        const int zn = L::D == 3 ? wrap(z, L::cz[i], g.nz) : 0;
+        const size_t nsite = (size_t)xn + (size_t)g.nx * ((size_t)yn + (size_t)g.ny * (size_t)zn);
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const double w = (double)L::w36[i] / 36.0;
+            store_pop<L, S>(dst, g.nsites, s, i, site, (Real)(w * rho[(size_t)s * g.nsites + nsite]),
+                            s == 0 ? ref0 : ref1);
+        }
+    }
+}
+
+// Pre-collision population (s, i) of every site to FP64: out[r] = buf_i(r - c_i).
+template <class L, class S>
+__global__ __launch_bounds__(256) void gather_pop_kernel(const S *src, double *out, Geom g, int s, int i,
+                                                         typename Storage<S>::Real ref)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y, z = blockIdx.z;
+    if (x >= g.nx) return;
+    const int cx = L::cx[i], cy = L::cy[i], cz = L::cz[i];
+    const int xs = wrap(x, -cx, g.nx), ys = wrap(y, -cy, g.ny), zs = L::D == 3 ? wrap(z, -cz, g.nz) : 0;
+    const size_t src_site = (size_t)xs + (size_t)g.nx * ((size_t)ys + (size_t)g.ny * (size_t)zs);
+    const size_t site = (size_t)x + (size_t)g.nx * ((size_t)y + (size_t)g.ny * (size_t)z);
+    using Real = typename Storage<S>::Real;
+    Real v = Storage<S>::load(src, ((size_t)(s * L::Q + i)) * g.nsites + src_site);
+    double d = (double)v;
+    if (Storage<S>::deviation) d = (double)(v + Real(L::w36[i]) / Real(36) * ref);
+    out[site] = d;
+}
+
+// Inverse of gather_pop_kernel: buf_i(r) = in[r + c_i].
+template <class L, class S>
+__global__ __launch_bounds__(256) void scatter_pop_kernel(S *dst, const double *in, Geom g, int s, int i,
+                                                          typename Storage<S>::Real ref)
+{
+    using Real = typename Storage<S>::Real;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y, z = blockIdx.z;
+    if (x >= g.nx) return;
+    const int cx = L::cx[i], cy = L::cy[i], cz = L::cz[i];
+    const int xn = wrap(x, cx, g.nx), yn = wrap(y, cy, g.ny), zn = L::D == 3 ? wrap(z, cz, g.nz) : 0;
+    const size_t nsite = (size_t)xn + (size_t)g.nx * ((size_t)yn + (size_t)g.ny * (size_t)zn);
+    const size_t site = (size_t)x + (size_t)g.nx * ((size_t)y + (size_t)g.ny * (size_t)z);
+    store_pop<L, S>(dst, g.nsites, s, i, site, (Real)in[nsite], ref);
+}
+
+}  // namespace fmlb

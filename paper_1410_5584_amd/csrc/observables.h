@@ -1,0 +1,338 @@
+// Observables of the stored pre-collision state: moment fields, FP64 global
+// sums, mode statistics and structure factors (Sec. VI A).  Every kernel pulls
+// the populations (pull layout, see storage.h) so the results refer to
+// f_bar(r, n).
+#pragma once
+
+#include "kernels.h"
+
+namespace fmlb {
+
+constexpr int kRedBlock = 256;
+
+template <class L, class S>
+__device__ __forceinline__ void pull_site_f64(const S *src, const Geom &g, int x, int y, int z,
+                                              const typename Storage<S>::Real (&ref)[2], double (&f)[2][L::Q])
+{
+    using Real = typename Storage<S>::Real;
+    Real fr[2][L::Q];
+    pull_site<L, S>(src, g, x, y, z, ref, fr);
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) f[s][i] = (double)fr[s][i];
+}
+
+// Site coordinates of linear index t (grid-stride helpers).
+__device__ __forceinline__ void site_xyz(size_t t, const Geom &g, int &x, int &y, int &z)
+{
+    x = (int)(t % (size_t)g.nx);
+    const size_t r = t / (size_t)g.nx;
+    y = (int)(r % (size_t)g.ny);
+    z = (int)(r / (size_t)g.ny);
+}
+
+// which = 0, 1: rho_sigma; 2 + s * D + alpha: j_bar_sigma,alpha.  FP64.
+template <class L, class S>
+__global__ __launch_bounds__(256) void moment_field_kernel(const S *src, double *out, Geom g, int which,
+                                                           typename Storage<S>::Real ref0,
+                                                           typename Storage<S>::Real ref1)
+{
+    using Real = typename Storage<S>::Real;
+    const Real ref[2] = {ref0, ref1};
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < g.nsites; t += (size_t)gridDim.x * blockDim.x) {
+        int x, y, z;
+        site_xyz(t, g, x, y, z);
+        double f[2][L::Q];
+        pull_site_f64<L, S>(src, g, x, y, z, ref, f);
+        double v = 0;
+        if (which < 2) {
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i) v += f[which][i];
+        } else {
+            const int s = (which - 2) / L::D, al = (which - 2) % L::D;
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i) {
+                const int c = al == 0 ? L::cx[i] : al == 1 ? L::cy[i] : L::cz[i];
+                if (c) v += c > 0 ? f[s][i] : -f[s][i];
+            }
+        }
+        out[t] = v;
+    }
+}
+
+template <int NV>
+__device__ __forceinline__ void block_reduce_store(double (&v)[NV], double *partial)
+{
+    __shared__ double sh[kRedBlock];
+#pragma unroll 1
+    for (int k = 0; k < NV; ++k) {
+        sh[threadIdx.x] = v[k];
+        __syncthreads();
+        for (int w = kRedBlock / 2; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) partial[(size_t)blockIdx.x * NV + k] = sh[0];
+        __syncthreads();
+    }
+}
+
+// Per-block partial sums of rho_1, rho_2, (j_bar_1 + j_bar_2)_alpha.
+template <class L, class S>
+__global__ __launch_bounds__(kRedBlock) void sums_kernel(const S *src, double *partial, Geom g,
+                                                         typename Storage<S>::Real ref0,
+                                                         typename Storage<S>::Real ref1)
+{
+    using Real = typename Storage<S>::Real;
+    const Real ref[2] = {ref0, ref1};
+    constexpr int NV = 2 + L::D;
+    double v[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = 0;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < g.nsites; t += (size_t)gridDim.x * blockDim.x) {
+        int x, y, z;
+        site_xyz(t, g, x, y, z);
+        double f[2][L::Q];
+        pull_site_f64<L, S>(src, g, x, y, z, ref, f);
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i) {
+                v[s] += f[s][i];
+                if (L::cx[i]) v[2] += L::cx[i] * f[s][i];
+                if (L::cy[i]) v[3] += L::cy[i] * f[s][i];
+                if (L::D == 3 && L::cz[i]) v[NV - 1] += L::cz[i] * f[s][i];
+            }
+    }
+    block_reduce_store<NV>(v, partial);
+}
+
+// Fixed-order final reduction: out[k] = sum over blocks of partial[b][k];
+// if accum != nullptr, accum[k] += that sum instead.
+__global__ __launch_bounds__(kRedBlock) void finalize_kernel(const double *partial, int nblocks, int nv,
+                                                             double *out, double *accum)
+{
+    __shared__ double sh[kRedBlock];
+    for (int k = 0; k < nv; ++k) {
+        double v = 0;
+        for (int b = threadIdx.x; b < nblocks; b += blockDim.x) v += partial[(size_t)b * nv + k];
+        sh[threadIdx.x] = v;
+        __syncthreads();
+        for (int w = kRedBlock / 2; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            if (accum)
+                accum[k] += sh[0];
+            else
+                out[k] = sh[0];
+        }
+        __syncthreads();
+    }
+}
+
+// Per-block partial sums of m_a and m_a^2 (m_a = sum_i T_ai f_bar_i, Eq. (80))
+// for both species: 4Q values laid out [s][a][moment].
+template <class L, class S>
+__global__ __launch_bounds__(kRedBlock) void mode_stats_kernel(const S *src, double *partial, Geom g,
+                                                               typename Storage<S>::Real ref0,
+                                                               typename Storage<S>::Real ref1)
+{
+    using Real = typename Storage<S>::Real;
+    const Real ref[2] = {ref0, ref1};
+    constexpr int NV = 4 * L::Q;
+    double v[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = 0;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < g.nsites; t += (size_t)gridDim.x * blockDim.x) {
+        int x, y, z;
+        site_xyz(t, g, x, y, z);
+        double f[2][L::Q];
+        pull_site_f64<L, S>(src, g, x, y, z, ref, f);
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int a = 0; a < L::Q; ++a) {
+                double m = 0;
+#pragma unroll
+                for (int i = 0; i < L::Q; ++i)
+                    if (L::T[a][i]) m += (double)L::T[a][i] * f[s][i];
+                v[(s * L::Q + a) * 2] += m;
+                v[(s * L::Q + a) * 2 + 1] += m * m;
+            }
+    }
+    block_reduce_store<NV>(v, partial);
+}
+
+// counts[0]: sites where not (rho_1 > 0 and rho_2 > 0); counts[1]: sites with a
+// non-finite population.  Block partials as doubles (exact for counts < 2^53).
+template <class L, class S>
+__global__ __launch_bounds__(kRedBlock) void health_kernel(const S *src, double *partial, Geom g,
+                                                           typename Storage<S>::Real ref0,
+                                                           typename Storage<S>::Real ref1)
+{
+    using Real = typename Storage<S>::Real;
+    const Real ref[2] = {ref0, ref1};
+    double v[2] = {0, 0};
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < g.nsites; t += (size_t)gridDim.x * blockDim.x) {
+        int x, y, z;
+        site_xyz(t, g, x, y, z);
+        Real f[2][L::Q];
+        pull_site<L, S>(src, g, x, y, z, ref, f);
+        bool bad = false;
+        Real r[2];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            Real acc = 0;
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i) {
+                acc += f[s][i];
+                bad |= !isfinite(f[s][i]);
+            }
+            r[s] = acc;
+        }
+        if (!(r[0] > Real(0) && r[1] > Real(0))) v[0] += 1;
+        if (bad) v[1] += 1;
+    }
+    block_reduce_store<2>(v, partial);
+}
+
+// ---------------------------------------------------------------------------
+// Structure factors.  Fields are built as complex FP64 arrays, transformed by
+// separable line DFTs along x, y, z, and accumulated as products / sites.
+// ---------------------------------------------------------------------------
+
+// Scalar field of the pre-collision state into A (imaginary part 0).
+// kind 0: rho_s; 1: j_bar_s,alpha; 2: physical barycentric velocity
+// (j_bar_1 + j_bar_2 + (F_1 + F_2)/2)_alpha / rho_t with the force of Eq. (87)
+// from the density buffer rho[2][sites].
+template <class L, class S>
+__global__ __launch_bounds__(256) void sk_field_kernel(const S *src, const typename Storage<S>::Real *rho,
+                                                       double2 *A, Geom g, int kind, int s, int al, double negG,
+                                                       typename Storage<S>::Real ref0,
+                                                       typename Storage<S>::Real ref1)
+{
+    using Real = typename Storage<S>::Real;
+    const Real ref[2] = {ref0, ref1};
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < g.nsites; t += (size_t)gridDim.x * blockDim.x) {
+        int x, y, z;
+        site_xyz(t, g, x, y, z);
+        double f[2][L::Q];
+        pull_site_f64<L, S>(src, g, x, y, z, ref, f);
+        double v = 0;
+        if (kind == 0) {
+#pragma unroll
+            for (int i = 0; i < L::Q; ++i) v += f[s][i];
+        } else {
+            double jt[2] = {0, 0}, r[2] = {0, 0};
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int i = 0; i < L::Q; ++i) {
+                    const int c = al == 0 ? L::cx[i] : al == 1 ? L::cy[i] : L::cz[i];
+                    r[q] += f[q][i];
+                    if (c) jt[q] += c > 0 ? f[q][i] : -f[q][i];
+                }
+            if (kind == 1) {
+                v = jt[s];
+            } else {
+                double a[2] = {0, 0};
+#pragma unroll
+                for (int i = 1; i < L::Q; ++i) {
+                    const int c = al == 0 ? L::cx[i] : al == 1 ? L::cy[i] : L::cz[i];
+                    if (!c) continue;
+                    const int xn = wrap(x, L::cx[i], g.nx), yn = wrap(y, L::cy[i], g.ny);
+                    const int zn = L::D == 3 ? wrap(z, L::cz[i], g.nz) : 0;
+                    const size_t nsite = (size_t)xn + (size_t)g.nx * ((size_t)yn + (size_t)g.ny * (size_t)zn);
+                    const double w = (double)L::w36[i] / 36.0;
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) a[q] += c * w * (double)rho[(size_t)(1 - q) * g.nsites + nsite];
+                }
+                const double Ft = negG * (r[0] * a[0] + r[1] * a[1]);
+                const double rt = r[0] + r[1];
+                v = rt > 0 ? (jt[0] + jt[1] + 0.5 * Ft) / rt : 0.0;
+            }
+        }
+        A[t] = make_double2(v, 0.0);
+    }
+}
+
+// In-place DFT of every line along one axis: X[k] = sum_n x[n] e^{-2 pi i k n / L}.
+// Line l's elements are base(l) + m * stride, m < L.  One workgroup per line;
+// power-of-two L use a radix-2 Stockham FFT in LDS, other lengths a direct
+// sum against an LDS twiddle table.  L <= 2048.
+constexpr int kMaxLine = 2048;
+
+__global__ __launch_bounds__(256) void dft_lines_kernel(double2 *A, int L, size_t stride, int inner,
+                                                        size_t inner_stride, size_t outer_stride)
+{
+    extern __shared__ double2 lds[];  // 2 * L (data, ping-pong / twiddles)
+    const size_t line = blockIdx.x;
+    const size_t base = (line % (size_t)inner) * inner_stride + (line / (size_t)inner) * outer_stride;
+    double2 *a = lds;
+    double2 *b = lds + L;
+    for (int m = threadIdx.x; m < L; m += blockDim.x) a[m] = A[base + (size_t)m * stride];
+    __syncthreads();
+    if ((L & (L - 1)) == 0) {
+        // Stockham radix-2: at stage with half-size h, element pairs (j, j + L/2)
+        // combine into positions of blocks of size 2h.
+        for (int h = 1; h < L; h <<= 1) {
+            for (int t = threadIdx.x; t < L / 2; t += blockDim.x) {
+                const int k = t % h;          // position within the current block
+                const int blk = t / h;
+                const double2 u = a[t];
+                const double2 v = a[t + L / 2];
+                double sn, cs;
+                sincospi(-(double)k / (double)h, &sn, &cs);
+                const double2 tv = make_double2(v.x * cs - v.y * sn, v.x * sn + v.y * cs);
+                b[blk * 2 * h + k] = make_double2(u.x + tv.x, u.y + tv.y);
+                b[blk * 2 * h + k + h] = make_double2(u.x - tv.x, u.y - tv.y);
+            }
+            __syncthreads();
+            double2 *tmp = a;
+            a = b;
+            b = tmp;
+        }
+        for (int m = threadIdx.x; m < L; m += blockDim.x) A[base + (size_t)m * stride] = a[m];
+    } else {
+        for (int m = threadIdx.x; m < L; m += blockDim.x) {
+            double sn, cs;
+            sincospi(-2.0 * (double)m / (double)L, &sn, &cs);
+            b[m] = make_double2(cs, sn);
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < L; k += blockDim.x) {
+            double re = 0, im = 0;
+            int idx = 0;
+            for (int n = 0; n < L; ++n) {
+                const double2 x = a[n], t = b[idx];
+                re += x.x * t.x - x.y * t.y;
+                im += x.x * t.y + x.y * t.x;
+                idx += k;
+                if (idx >= L) idx -= L;
+            }
+            A[base + (size_t)k * stride] = make_double2(re, im);
+        }
+    }
+}
+
+// acc[t] += scale * Re(A conj(B)) (B = A for an auto spectrum); k = 0 (the
+// mean, removed by the definition dX = X - <X>) is skipped.
+__global__ __launch_bounds__(256) void sk_accum_kernel(const double2 *A, const double2 *B, double *acc,
+                                                       size_t n, double scale)
+{
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
+        if (t == 0) continue;
+        const double2 a = A[t], b = B[t];
+        acc[t] += scale * (a.x * b.x + a.y * b.y);
+    }
+}
+
+__global__ __launch_bounds__(256) void fill_kernel(double *p, size_t n, double v)
+{
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) p[t] = v;
+}
+
+}  // namespace fmlb

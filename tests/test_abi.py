@@ -1,0 +1,75 @@
+"""CPU checks of the C ABI: the library loads, exports every entry point the
+header declares, sizes buffers, and rejects invalid parameters before touching
+the GPU.  No compute call is made here."""
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fmlb.h")
+
+
+@pytest.fixture(scope="module")
+def fm():
+    import paper_1410_5584_amd as fm
+    if not os.path.exists(fm.LIB_PATH):
+        from paper_1410_5584_amd import build
+        build.build()
+    fm.lib()
+    return fm
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fmlb_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol(fm):
+    names = _declared()
+    assert len(names) >= 30
+    out = subprocess.run(["nm", "-D", "--defined-only", fm.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(re.findall(r"\b(fmlb_[a-z0-9_]+)\b", out))
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    # and the binding wraps each of them under the same name
+    for n in names:
+        assert n in fm._SIGNATURES, n
+
+
+def test_required_bytes(fm):
+    p = fm.Params(lattice="d3q19", storage="f32", nx=256, ny=256, nz=256)
+    n = 256 ** 3
+    assert fm.fmlb_required_bytes(p.c(), 0) == 2 * 19 * n * 4
+    assert fm.fmlb_required_bytes(p.c(), 1) == 2 * 19 * n * 4
+    assert fm.fmlb_required_bytes(p.c(), 2) > 2 * n * 4
+    p16 = fm.Params(lattice="d3q19", storage="bf16", nx=256, ny=256, nz=256)
+    assert fm.fmlb_required_bytes(p16.c(), 0) == 2 * 19 * n * 2
+    p64 = fm.Params(lattice="d2q9", storage="f64", nx=64, ny=64)
+    assert fm.fmlb_required_bytes(p64.c(), 0) == 2 * 9 * 64 * 64 * 8
+
+
+@pytest.mark.parametrize("bad", [
+    dict(tau=(0.5, 1.0)), dict(tau=(1.0, 0.4)), dict(tau_d=0.5), dict(kT=-1e-5),
+    dict(nx=0), dict(lattice="d2q9", nz=2), dict(G=float("nan")),
+])
+def test_invalid_parameters_rejected(fm, bad):
+    p = fm.Params(**bad)
+    assert fm.fmlb_required_bytes(p.c(), 0) == 0
+    with pytest.raises(fm.FmlbError) as e:
+        fm.fmlb_create(p.c(), 0, [256, 512, 768])
+    assert e.value.status == fm.FMLB_E_INVALID
+
+
+def test_null_and_alignment_errors(fm):
+    p = fm.Params()
+    with pytest.raises(fm.FmlbError) as e:
+        fm.fmlb_create(p.c(), 0, [0, 512, 768])
+    assert e.value.status == fm.FMLB_E_NULL
+    with pytest.raises(fm.FmlbError) as e:
+        fm.fmlb_create(p.c(), 0, [256 + 8, 512, 768])
+    assert e.value.status == fm.FMLB_E_INVALID
+    assert fm.lib().fmlb_status_string(fm.FMLB_E_STATE).decode() == "populations not initialised"

@@ -1,0 +1,297 @@
+"""GPU parity of the HIP hot path against the FP64 oracle, through the C ABI.
+
+Same seeded inputs on both sides (workloads module), element-by-element
+comparison of the pre-collision populations.  Tolerances:
+  FP64 storage: max |f_gpu - f_orc| <= 1e-12 max |f_orc| (rounding order and
+  last-ulp differences of log / sin / cos / sqrt between the device and the
+  host C library, in a contractive map).
+  FP32 and 16-bit storage: the bounds stated next to each test, derived from
+  the storage rounding (2^-24, 2^-9 and 2^-12 relative) accumulated over the
+  steps of the test.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def fm():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1410_5584_amd as fm
+    fm.lib()
+    return fm
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _pair(fm, orc, lattice, shape, storage="f64", init="perturbed", seed_init=5, **phys):
+    nz, ny, nx = shape
+    import workloads
+    r1, r2 = workloads.initial_density(shape, init, seed=seed_init, amplitude=0.05)
+    gp = fm.Params(lattice=lattice, storage=storage, nx=nx, ny=ny, nz=nz, **phys)
+    g = fm.Lattice(gp)
+    g.init_density(r1, r2)
+    op = orc.Params(lattice=0 if lattice == "d2q9" else 1, nx=nx, ny=ny, nz=nz,
+                    **{k: v for k, v in phys.items() if k != "rho_ref"})
+    o = orc.Sim(op)
+    o.init_density(r1, r2)
+    return g, o
+
+
+def _relerr(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def test_c0_parity_fp64(fm, orc):
+    """The C0 workload itself: D2Q9 64x64, FP64, G = 0, tau = 1, k_BT = 1e-4,
+    uniform start, seed 1, 1000 steps."""
+    _say("case c0 d2q9 64x64 f64 1000 steps")
+    g, o = _pair(fm, orc, "d2q9", (1, 64, 64), "f64", init="uniform", tau=(1.0, 1.0), tau_d=1.0, G=0.0,
+                 kT=1e-4, seed=1)
+    g.step(1000)
+    o.step(1000)
+    err = _relerr(g.populations(), o.populations())
+    _say("c0 max rel diff", err)
+    assert err <= 1e-12
+
+
+CASES_F64 = [
+    ("d2q9", (1, 23, 37), dict(tau=(0.8, 1.3), tau_d=0.9, G=0.6, kT=1e-4, seed=3), 200),
+    ("d2q9", (1, 7, 1), dict(tau=(0.7, 1.2), tau_d=1.1, G=0.3, kT=1e-3, seed=4), 50),
+    ("d2q9", (1, 1, 1), dict(tau=(0.9, 1.4), tau_d=0.8, G=0.5, kT=1e-3, seed=5), 50),
+    ("d2q9", (1, 19, 70), dict(tau=(1.0, 1.0), tau_d=1.0, G=0.9, kT=0.0, seed=6), 100),
+    ("d2q9", (1, 16, 16), dict(tau=(1.0, 1.0), tau_d=1.0, G=0.0, kT=1e-4, seed=7, flags=2), 100),
+    ("d3q19", (9, 11, 13), dict(tau=(0.8, 1.3), tau_d=0.9, G=0.6, kT=1e-4, seed=3), 40),
+    ("d3q19", (4, 3, 70), dict(tau=(1.0, 1.0), tau_d=1.0, G=1.2, kT=1e-5, seed=8), 30),
+    ("d3q19", (1, 1, 1), dict(tau=(0.9, 1.4), tau_d=0.8, G=0.5, kT=1e-3, seed=5), 30),
+    ("d3q19", (6, 5, 4), dict(tau=(0.8, 0.8), tau_d=0.8, G=0.7, kT=0.0, seed=1), 30),
+]
+
+
+@pytest.mark.parametrize("lattice,shape,phys,steps", CASES_F64)
+def test_parity_fp64(fm, orc, lattice, shape, phys, steps):
+    _say("case f64", lattice, shape, phys, steps)
+    g, o = _pair(fm, orc, lattice, shape, "f64", **phys)
+    g.step(steps)
+    o.step(steps)
+    err = _relerr(g.populations(), o.populations())
+    _say("max rel diff", err)
+    assert err <= 1e-12
+
+
+@pytest.mark.parametrize("lattice,shape,steps,tol", [
+    ("d2q9", (1, 80, 96), 200, 2e-5),
+    ("d3q19", (20, 18, 33), 50, 2e-5),
+])
+def test_parity_fp32(fm, orc, lattice, shape, steps, tol):
+    """FP32 storage and arithmetic, C1 physics (G = 0.5, tau = 0.8 / 1.2,
+    k_BT = 1e-5): bound 2e-5 of max |f| (about 340 units of 2^-24 at the
+    largest population, for rounding that accumulates in a contractive map
+    plus the FP32 Box-Muller error)."""
+    _say("case f32", lattice, shape, steps)
+    g, o = _pair(fm, orc, lattice, shape, "f32", tau=(0.8, 1.2), tau_d=1.0, G=0.5, kT=1e-5, seed=1)
+    g.step(steps)
+    o.step(steps)
+    err = _relerr(g.populations(), o.populations())
+    _say("max rel diff", err)
+    assert err <= tol
+
+
+@pytest.mark.parametrize("storage,tol", [("bf16", 3e-3), ("f16", 4e-4)])
+@pytest.mark.parametrize("lattice,shape", [("d3q19", (12, 10, 14)), ("d2q9", (1, 40, 36))])
+def test_parity_16bit_deviation(fm, orc, storage, tol, lattice, shape):
+    """16-bit deviation storage (f - w rho_ref), FP32 arithmetic, 10 steps
+    of C2 physics from a 5 % perturbed start: bound = tol * max |f|
+    (deviations up to ~0.05 w_i, rounding 2^-9 (bf16) / 2^-12 (f16) relative
+    to the deviation, accumulated over 10 steps)."""
+    _say("case", storage, lattice, shape)
+    g, o = _pair(fm, orc, lattice, shape, storage, tau=(1.0, 1.0), tau_d=1.0, G=1.2, kT=1e-5, seed=1,
+                 rho_ref=(1.0, 1.0))
+    g.step(10)
+    o.step(10)
+    err = _relerr(g.populations(), o.populations())
+    _say("max rel diff", err)
+    assert err <= tol
+
+
+def test_conservation_on_gpu(fm):
+    for storage, tol in (("f64", 1e-13), ("f32", 2e-6)):
+        _say("case conservation", storage)
+        p = fm.Params(lattice="d3q19", storage=storage, nx=24, ny=20, nz=16, tau=(0.8, 1.2), tau_d=0.9,
+                      G=0.8, kT=1e-4, seed=2)
+        g = fm.Lattice(p)
+        import workloads
+        r1, r2 = workloads.initial_density((16, 20, 24), "perturbed", seed=2)
+        g.init_density(r1, r2)
+        s0 = g.global_sums()
+        g.step(200)
+        s1 = g.global_sums()
+        scale = s0[:2].sum()
+        _say("drift", (s1 - s0) / scale)
+        assert np.all(np.abs(s1 - s0) <= tol * scale)
+
+
+def test_checkpoint_and_split_steps_bitwise(fm):
+    _say("case checkpoint")
+    p = fm.Params(lattice="d2q9", storage="f32", nx=50, ny=30, tau=(0.8, 1.2), G=0.5, kT=1e-5, seed=11)
+    g = fm.Lattice(p)
+    import workloads
+    r1, r2 = workloads.initial_density((1, 30, 50), "perturbed", seed=3)
+    g.init_density(r1, r2)
+    g.step(7)
+    raw, step = g.save_raw()
+    assert step == 7
+    g.step(13)
+    a = g.populations()
+    g.load_raw(raw, step)
+    for _ in range(13):
+        g.step(1)
+    b = g.populations()
+    assert np.array_equal(a, b)
+
+
+def test_observables_match_oracle(fm, orc):
+    """Moments, global sums, one-snapshot structure factors and mode sums of
+    the same FP64 state on both sides."""
+    _say("case observables")
+    shape = (1, 24, 32)
+    g, o = _pair(fm, orc, "d2q9", shape, "f64", tau=(0.8, 1.2), tau_d=1.0, G=0.5, kT=1e-4, seed=2)
+    g.step(30)
+    o.step(30)
+    rho_o, j_o, F_o = o.moments()
+    rho_g, j_g = g.moments()
+    assert np.max(np.abs(rho_g - rho_o)) < 1e-12
+    assert np.max(np.abs(j_g - j_o)) < 1e-12
+    s = g.global_sums()
+    assert s[:2] == pytest.approx(rho_o.reshape(2, -1).sum(1), rel=1e-13)
+    assert np.allclose(s[2:], j_o.reshape(2, 2, -1).sum(2).sum(0), atol=1e-12)
+    g.sk_accumulate()
+    checks = {
+        "rho1rho1": orc.structure_factor(rho_o[0, 0]),
+        "rho2rho2": orc.structure_factor(rho_o[1, 0]),
+        "rho1rho2": orc.structure_factor(rho_o[0, 0], rho_o[1, 0]),
+        "j1j1": 0.5 * sum(orc.structure_factor(j_o[0, a, 0]) for a in range(2)),
+        "j2j2": 0.5 * sum(orc.structure_factor(j_o[1, a, 0]) for a in range(2)),
+        "j1j2": 0.5 * sum(orc.structure_factor(j_o[0, a, 0], j_o[1, a, 0]) for a in range(2)),
+    }
+    vb = (j_o[0] + j_o[1] + 0.5 * (F_o[0] + F_o[1])) / (rho_o[0] + rho_o[1])
+    checks["vbvb"] = 0.5 * sum(orc.structure_factor(vb[a, 0]) for a in range(2))
+    for name, ref in checks.items():
+        got, n = g.sk(name)
+        assert n == 1
+        got = got[0]
+        ref = ref.copy()
+        ref[0, 0] = 0.0
+        assert np.max(np.abs(got - ref)) <= 1e-9 * np.max(np.abs(ref)), name
+    g.mode_accumulate()
+    ratios, n = g.mode_variances()
+    m = o.mode_moments().reshape(2, 9, -1)
+    var = m.var(axis=2)
+    ref = var / (o.N * 3 * 1e-4 * 1.0)
+    assert np.allclose(ratios, ref, rtol=1e-9)
+
+
+def test_health_counts(fm):
+    _say("case health")
+    p = fm.Params(lattice="d2q9", storage="f64", nx=8, ny=8)
+    g = fm.Lattice(p)
+    g.init_density(1.0, 1.0)
+    assert g.health() == (0, 0)
+    f = g.populations()
+    f[0, :, 0, 2, 3] = -0.1        # negative density of species 1 at one site
+    f[1, 4, 0, 5, 5] = np.nan      # a non-finite population at another
+    g.set_populations(f, 0)
+    assert g.health() == (2, 1)
+
+
+def _sampled_full_size(fm, orc, lattice, shape, storage, phys, steps, n_samples, tol, tile=None):
+    """Run the full-size lattice on the GPU in the benchmark's launch shape,
+    then check one more step at sampled sites against the oracle's collision
+    of the same (GPU-produced) pre-collision state."""
+    import workloads
+    nz, ny, nx = shape
+    r1, r2 = workloads.initial_density(shape, "perturbed", seed=phys["seed"], amplitude=0.01)
+    g = fm.Lattice(fm.Params(lattice=lattice, storage=storage, nx=nx, ny=ny, nz=nz, **phys))
+    if tile is not None:
+        g.set_tile(*tile)
+    g.init_density(r1, r2)
+    g.step(steps)
+    f_n = g.populations()
+    g.step(1)
+    f_n1 = g.populations()
+    o = orc.Sim(orc.Params(lattice=0 if lattice == "d2q9" else 1, nx=nx, ny=ny, nz=nz,
+                           **{k: v for k, v in phys.items() if k != "rho_ref"}))
+    o.set_populations(f_n, steps)
+    del f_n
+    rng = np.random.default_rng(0)
+    sites = rng.integers(0, nx * ny * nz, size=n_samples)
+    sites[:4] = [0, nx - 1, nx * ny * nz - 1, (nx * ny * nz) // 2]
+    c = o.c
+    worst = 0.0
+    fmax = np.max(np.abs(f_n1))
+    flat = f_n1.reshape(2, o.Q, -1)
+    for s in sites:
+        x, y, z = s % nx, (s // nx) % ny, s // (nx * ny)
+        for i in range(o.Q):
+            xs, ys, zs = (x - c[i, 0]) % nx, (y - c[i, 1]) % ny, (z - c[i, 2]) % nz
+            src = xs + nx * (ys + ny * zs)
+            fo = o.collide_site(src)[:, i]
+            worst = max(worst, float(np.max(np.abs(flat[:, i, s] - fo))))
+    _say("sampled max diff / max|f|", worst / fmax)
+    assert worst <= tol * fmax
+
+
+def test_full_size_c1_sampled(fm, orc):
+    _say("case full-size c1 d2q9 1024^2 f32")
+    _sampled_full_size(fm, orc, "d2q9", (1, 1024, 1024), "f32",
+                       dict(tau=(0.8, 1.2), tau_d=1.0, G=0.5, kT=1e-5, seed=1), 20, 400, 2e-6)
+
+
+def test_full_size_c2_sampled(fm, orc):
+    _say("case full-size c2 d3q19 256^3 f32")
+    _sampled_full_size(fm, orc, "d3q19", (256, 256, 256), "f32",
+                       dict(tau=(1.0, 1.0), tau_d=1.0, G=1.2, kT=1e-5, seed=1), 3, 300, 2e-6)
+
+
+@pytest.mark.parametrize("lattice,shape,tiles", [
+    ("d3q19", (20, 19, 70), [(1, 0, 0), (64, 4, 7), (64, 8, 32), (32, 8, 3), (32, 16, 5)]),
+    ("d2q9", (1, 37, 300), [(1, 0, 0), (64, 1, 5), (128, 1, 16), (256, 1, 2)]),
+])
+@pytest.mark.parametrize("storage", ["f32", "bf16", "f16"])
+def test_launch_shape_invariance_bitwise(fm, lattice, shape, tiles, storage):
+    """Every fused launch shape gives the same bits as the two-pass form:
+    ragged tiles, short and long marches.  (FP64 storage always runs the
+    two-pass form.)"""
+    import workloads
+    _say("case shapes", lattice, shape, storage)
+    nz, ny, nx = shape
+    r1, r2 = workloads.initial_density(shape, "perturbed", seed=9, amplitude=0.05)
+    ref = None
+    for t in tiles:
+        g = fm.Lattice(fm.Params(lattice=lattice, storage=storage, nx=nx, ny=ny, nz=nz, tau=(0.8, 1.2),
+                                 tau_d=0.9, G=0.9, kT=1e-4, seed=4))
+        g.set_tile(*t)
+        g.init_density(r1, r2)
+        g.step(6)
+        raw, _ = g.save_raw()
+        g.close()
+        if ref is None:
+            ref = raw
+        else:
+            assert np.array_equal(raw, ref), t
+
+
+def test_fp64_rejects_fused_shapes(fm):
+    g = fm.Lattice(fm.Params(lattice="d3q19", storage="f64", nx=8, ny=8, nz=8))
+    g.set_tile(1, 0, 0)
+    with pytest.raises(fm.FmlbError):
+        g.set_tile(64, 4, 8)

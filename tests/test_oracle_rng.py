@@ -46,16 +46,29 @@ def test_philox_matches_rocrand(orc, rocrand_ref):
 
 
 def test_uniform_extraction(orc):
+    """Word w of block j gives the pair (u_2w', u_2w'+1) from its high and
+    low 16 bits, u = (2U + 1) / 2^17."""
     seed, site, step = 0x1234_5678_9ABC, 77, 3_000_000_123
-    u = orc.uniforms(seed, site, step, 15)
+    u = orc.uniforms(seed, site, step, 24)
     key = [seed & 0xFFFFFFFF, seed >> 32]
     for j in range(3):
         x = orc.philox([site, step & 0xFFFFFFFF, j, step >> 32], key)
-        U = [x[0] >> 9, x[1] >> 9, x[2] >> 9, x[3] >> 9,
-             (x[0] & 0x1FF) | ((x[1] & 0x1FF) << 9) | ((x[2] & 0x1F) << 18)]
-        for t in range(5):
-            assert u[5 * j + t] == (2 * U[t] + 1) / 2.0 ** 24
+        for t in range(4):
+            k = 8 * j + 2 * t
+            assert u[k] == (2 * (x[t] >> 16) + 1) / 2.0 ** 17
+            assert u[k + 1] == (2 * (x[t] & 0xFFFF) + 1) / 2.0 ** 17
     assert np.all(u > 0) and np.all(u < 1)
+
+
+def test_normal_tail_bound_and_variance_bias(orc):
+    """16-bit uniforms cap |z| at sqrt(2 ln 2^17) = 4.85; the variance of the
+    discrete Box-Muller radius differs from 2 by less than 1e-4 (midpoint sum
+    of -2 ln u over the 2^16 grid values)."""
+    z = np.concatenate([orc.normals(3, s, 1, 33) for s in range(3000)])
+    assert np.max(np.abs(z)) <= np.sqrt(2 * np.log(2.0 ** 17)) + 1e-12
+    U = np.arange(2 ** 16)
+    mean_r2 = np.mean(-2 * np.log((2 * U + 1) / 2.0 ** 17))
+    assert abs(mean_r2 - 2.0) < 1e-4
 
 
 def _many_normals(orc, n_sites=20000, K=14, seed=9, step=5):
