@@ -213,36 +213,69 @@ const char *fmlb_status_string(fmlb_status s);
 int32_t fmlb_last_hip_error(void);
 
 /* ------------------------------------------------------------------------ */
-/* Batched replicas: many independent D2Q9 lattices (square or rectangular,  */
-/* FP32 storage) with their own seed, k_BT and G, stepped together by one    */
-/* launch per step over a tile work list covering every replica.  Each       */
-/* replica evolves exactly as it would alone (the noise counter uses the     */
-/* replica's own site index and seed).                                       */
+/* Batched replicas (many independent small lattices, e.g. a parameter scan   */
+/* of the Sec. VI A equipartition and structure-factor checks): D2Q9          */
+/* lattices of any nx x ny with FP32 storage, each with its own seed, k_B T,  */
+/* G and relaxation times, advanced together by ONE launch per step over a    */
+/* work list of (replica, tile, chunk) items.  Each item runs the same        */
+/* per-tile code as the single-lattice fused step with the replica's own      */
+/* geometry, parameters, seed and site numbering, so replica r evolves bit    */
+/* for bit as an fmlb_ctx created from p[r] would (same step numbers).        */
+/*                                                                            */
+/* Layout: buffers A and B each hold every replica's [2][9][sites_r] block,   */
+/* in replica order, each block starting on a 256-byte boundary.  The         */
+/* pre-collision state of step n is in buffer (n mod 2).  The step number     */
+/* also lives in the scratch buffer, read by every step launch, so the steps  */
+/* can be replayed from a captured HIP graph.                                 */
 /* ------------------------------------------------------------------------ */
 typedef struct fmlb_batch fmlb_batch;
 
-/* Bytes of buffer `which` (FMLB_BUF_*) for n replicas described by p[n]
- * (every p[r] must be D2Q9 with storage FMLB_F32). */
+/* Bytes of buffer `which` (FMLB_BUF_*) for n replicas p[0..n-1]; 0 if any
+ * p[r] is not a valid D2Q9 / FMLB_F32 lattice or n is outside [1, 65535]. */
 size_t fmlb_batch_required_bytes(const fmlb_params *p, int n, int which);
+
+/* Borrow three 256-byte-aligned device buffers of at least the required
+ * sizes; the replica parameters are copied.  The batch starts at step 0 with
+ * no replica initialised.  Synchronises.  FMLB_E_INVALID as for
+ * fmlb_batch_required_bytes or a misaligned buffer. */
 fmlb_status fmlb_batch_create(const fmlb_params *p, int n, void *hip_stream,
                               void *const dev_buf[3], fmlb_batch **out);
 void fmlb_batch_destroy(fmlb_batch *b);
-/* rho[sites_r] per species, as fmlb_init_density, for replica r. */
+int fmlb_batch_size(const fmlb_batch *b);
+int64_t fmlb_batch_total_sites(const fmlb_batch *b);
+int64_t fmlb_batch_current_step(const fmlb_batch *b);
+
+/* Rest state f_bar_i = w_i rho_sigma of replica r from host FP64 densities
+ * rho1[sites_r], rho2[sites_r], placed at the batch's current step (the step
+ * counter is not reset).  Synchronises. */
 fmlb_status fmlb_batch_init_density(fmlb_batch *b, int r, const double *rho1, const double *rho2);
-/* Advance every replica n steps.  use_graph != 0 replays a captured HIP
- * graph of the step launch(es) instead of launching eagerly. */
+
+/* Advance every replica n steps (asynchronous).  use_graph != 0 replays a
+ * HIP graph of 32 steps on the batch's stream for each whole group of 32
+ * (recorded at first use on a private stream the batch owns) and launches
+ * the rest directly; the results are identical.  FMLB_E_STATE until every
+ * replica has been initialised. */
 fmlb_status fmlb_batch_step(fmlb_batch *b, int64_t n, int use_graph);
+
+/* Work-list shape: tile_x sites per workgroup row (64, 128 or 256) and
+ * `march` rows walked per item (1..4096); 0 = default for each.  Results do
+ * not depend on it.  Discards a captured graph. */
+fmlb_status fmlb_batch_set_tile(fmlb_batch *b, int tile_x, int march);
+
+/* As fmlb_get_populations, for replica r.  Synchronises. */
 fmlb_status fmlb_batch_get_populations(fmlb_batch *b, int r, double *host, size_t bytes);
+
+/* As fmlb_global_sums, for replica r: out[4] = sum rho_1, sum rho_2,
+ * sum (j_bar_1 + j_bar_2)_x, _y.  Synchronises. */
 fmlb_status fmlb_batch_global_sums(fmlb_batch *b, int r, double *out);
-/* Per-replica equipartition: accumulate, then out[2][9] ratios as
- * fmlb_mode_variances for replica r (normalised with that replica's k_BT
- * and rho_ref). */
+
+/* Equipartition statistics of every replica: accumulate adds the current
+ * state's per-replica mode sums (as fmlb_mode_accumulate); variances gives
+ * replica r's out[2][9] normalised with its own k_B T and rho_ref (as
+ * fmlb_mode_variances); reset clears every replica's sums. */
 fmlb_status fmlb_batch_mode_accumulate(fmlb_batch *b);
 fmlb_status fmlb_batch_mode_variances(fmlb_batch *b, int r, double *out, int64_t *n_samples);
-/* Tile work list shape (tile_x sites per workgroup row, tile_y rows); 0 =
- * default.  Results do not depend on it. */
-fmlb_status fmlb_batch_set_tile(fmlb_batch *b, int tile_x, int tile_y);
-int64_t fmlb_batch_total_sites(const fmlb_batch *b);
+fmlb_status fmlb_batch_reset_modes(fmlb_batch *b);
 
 #ifdef __cplusplus
 }

@@ -88,8 +88,11 @@ _SIGNATURES = {
     "fmlb_batch_global_sums": (ctypes.c_int32, [_vp, ctypes.c_int, _dp]),
     "fmlb_batch_mode_accumulate": (ctypes.c_int32, [_vp]),
     "fmlb_batch_mode_variances": (ctypes.c_int32, [_vp, ctypes.c_int, _dp, _i64p]),
+    "fmlb_batch_reset_modes": (ctypes.c_int32, [_vp]),
     "fmlb_batch_set_tile": (ctypes.c_int32, [_vp, ctypes.c_int, ctypes.c_int]),
+    "fmlb_batch_size": (ctypes.c_int, [_vp]),
     "fmlb_batch_total_sites": (ctypes.c_int64, [_vp]),
+    "fmlb_batch_current_step": (ctypes.c_int64, [_vp]),
 }
 
 
@@ -117,6 +120,17 @@ def _check(fn: str, status: int):
 def _f64(a) -> np.ndarray:
     a = np.ascontiguousarray(a, dtype=np.float64)
     return a
+
+
+def _as_field(x, shape) -> np.ndarray:
+    """A scalar broadcast to `shape`, or an array of that many values reshaped."""
+    x = np.asarray(x, dtype=np.float64)
+    n = int(np.prod(shape))
+    if x.size == n:
+        return np.ascontiguousarray(x.reshape(shape))
+    if x.size == 1:
+        return np.full(shape, float(x.reshape(-1)[0]))
+    raise ValueError(f"field of {x.size} values for a lattice of shape {shape}")
 
 
 def _ptr(a: np.ndarray):
@@ -216,6 +230,75 @@ def fmlb_set_tile(ctx: int, tile_x: int, tile_y: int, march: int):
     _check("fmlb_set_tile", lib().fmlb_set_tile(_vp(ctx), tile_x, tile_y, march))
 
 
+def _params_array(ps):
+    arr = (fmlb_params * len(ps))(*ps)
+    return arr, ctypes.cast(arr, _pp)
+
+
+def fmlb_batch_required_bytes(ps, which: int) -> int:
+    arr, ptr = _params_array(ps)
+    return lib().fmlb_batch_required_bytes(ptr, len(ps), which)
+
+
+def fmlb_batch_create(ps, stream: int, bufs) -> int:
+    arr, ptr = _params_array(ps)
+    b = (_vp * 3)(*[_vp(int(x)) for x in bufs])
+    out = _vp()
+    _check("fmlb_batch_create", lib().fmlb_batch_create(ptr, len(ps), _vp(stream), b, ctypes.byref(out)))
+    return out.value
+
+
+def fmlb_batch_destroy(b: int):
+    lib().fmlb_batch_destroy(_vp(b))
+
+
+def fmlb_batch_size(b: int) -> int:
+    return lib().fmlb_batch_size(_vp(b))
+
+
+def fmlb_batch_total_sites(b: int) -> int:
+    return lib().fmlb_batch_total_sites(_vp(b))
+
+
+def fmlb_batch_current_step(b: int) -> int:
+    return lib().fmlb_batch_current_step(_vp(b))
+
+
+def fmlb_batch_init_density(b: int, r: int, rho1: np.ndarray, rho2: np.ndarray):
+    r1, r2 = _f64(rho1), _f64(rho2)
+    _check("fmlb_batch_init_density", lib().fmlb_batch_init_density(_vp(b), r, _ptr(r1), _ptr(r2)))
+
+
+def fmlb_batch_step(b: int, n: int, use_graph: bool):
+    _check("fmlb_batch_step", lib().fmlb_batch_step(_vp(b), int(n), 1 if use_graph else 0))
+
+
+def fmlb_batch_set_tile(b: int, tile_x: int, march: int):
+    _check("fmlb_batch_set_tile", lib().fmlb_batch_set_tile(_vp(b), tile_x, march))
+
+
+def fmlb_batch_get_populations(b: int, r: int, out: np.ndarray):
+    _check("fmlb_batch_get_populations", lib().fmlb_batch_get_populations(_vp(b), r, _ptr(out), out.nbytes))
+
+
+def fmlb_batch_global_sums(b: int, r: int, out: np.ndarray):
+    _check("fmlb_batch_global_sums", lib().fmlb_batch_global_sums(_vp(b), r, _ptr(out)))
+
+
+def fmlb_batch_mode_accumulate(b: int):
+    _check("fmlb_batch_mode_accumulate", lib().fmlb_batch_mode_accumulate(_vp(b)))
+
+
+def fmlb_batch_mode_variances(b: int, r: int, out: np.ndarray) -> int:
+    n = ctypes.c_int64()
+    _check("fmlb_batch_mode_variances", lib().fmlb_batch_mode_variances(_vp(b), r, _ptr(out), ctypes.byref(n)))
+    return n.value
+
+
+def fmlb_batch_reset_modes(b: int):
+    _check("fmlb_batch_reset_modes", lib().fmlb_batch_reset_modes(_vp(b)))
+
+
 # ---- convenience wrapper: torch-owned buffers, numpy host arrays ------------
 
 @dataclass
@@ -266,7 +349,10 @@ class Lattice:
             self.ctx = None
 
     def __del__(self):
-        self.close()
+        try:
+            self.close()
+        except Exception:  # interpreter shutdown: the library may already be gone
+            pass
 
     @property
     def step_count(self) -> int:
@@ -334,6 +420,83 @@ class Lattice:
 
     def set_tile(self, tile_x: int = 0, tile_y: int = 0, march: int = 0):
         fmlb_set_tile(self.ctx, tile_x, tile_y, march)
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+
+class Batch:
+    """Many independent D2Q9 FP32 lattices stepped by one launch per step.
+    params: a list of Params (lattice "d2q9", storage "f32", nz 1)."""
+
+    def __init__(self, params, device=None, stream=None):
+        import torch
+        self.params = list(params)
+        cps = [p.c() for p in self.params]
+        sizes = [fmlb_batch_required_bytes(cps, k) for k in range(3)]
+        if min(sizes) == 0:
+            raise FmlbError("fmlb_batch_required_bytes", FMLB_E_INVALID)
+        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.bufs = [torch.empty(s, dtype=torch.uint8, device=dev) for s in sizes]
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        self.b = fmlb_batch_create(cps, self.stream.cuda_stream, [x.data_ptr() for x in self.bufs])
+
+    def close(self):
+        if getattr(self, "b", None):
+            fmlb_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # interpreter shutdown: the library may already be gone
+            pass
+
+    def __len__(self):
+        return fmlb_batch_size(self.b)
+
+    @property
+    def total_sites(self) -> int:
+        return fmlb_batch_total_sites(self.b)
+
+    @property
+    def step_count(self) -> int:
+        return fmlb_batch_current_step(self.b)
+
+    def shape(self, r: int):
+        return (self.params[r].ny, self.params[r].nx)
+
+    def init_density(self, r: int, rho1, rho2):
+        sh = self.shape(r)
+
+        fmlb_batch_init_density(self.b, r, _as_field(rho1, sh), _as_field(rho2, sh))
+
+    def step(self, n: int = 1, use_graph: bool = False):
+        fmlb_batch_step(self.b, n, use_graph)
+
+    def set_tile(self, tile_x: int = 0, march: int = 0):
+        fmlb_batch_set_tile(self.b, tile_x, march)
+
+    def populations(self, r: int):
+        out = np.empty((2, 9, 1) + self.shape(r))
+        fmlb_batch_get_populations(self.b, r, out)
+        return out
+
+    def global_sums(self, r: int):
+        out = np.empty(4)
+        fmlb_batch_global_sums(self.b, r, out)
+        return out
+
+    def mode_accumulate(self):
+        fmlb_batch_mode_accumulate(self.b)
+
+    def mode_variances(self, r: int):
+        out = np.empty((2, 9))
+        n = fmlb_batch_mode_variances(self.b, r, out)
+        return out, n
+
+    def reset_modes(self):
+        fmlb_batch_reset_modes(self.b)
 
     def synchronize(self):
         self.stream.synchronize()

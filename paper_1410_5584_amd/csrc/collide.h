@@ -65,8 +65,29 @@ struct Phys {
     Real gain[2];        // sqrt((2 lambda - lambda^2) mu), mu = 3 k_B T
     Real sd_gain;        // sqrt((2 lambda_d - lambda_d^2) k_B T), 0 without momentum noise
     uint32_t key0, key1; // Philox key (seed)
-    int noisy;           // any thermal noise
 };
+
+// Reciprocal and square root.  FP32 uses the hardware approximations
+// (v_rcp_f32, v_sqrt_f32, both within 1 ulp): every operand here is a
+// positive density or -2 ln u of a 16-bit uniform, never denormal, so the
+// IEEE-exact sequences would only add range-fixup instructions.
+template <class Real>
+__device__ __forceinline__ Real rcp(Real x)
+{
+    if constexpr (sizeof(Real) == 4)
+        return __builtin_amdgcn_rcpf(x);
+    else
+        return Real(1) / x;
+}
+
+template <class Real>
+__device__ __forceinline__ Real root(Real x)
+{
+    if constexpr (sizeof(Real) == 4)
+        return __builtin_amdgcn_sqrtf(x);
+    else
+        return sqrt(x);
+}
 
 // Acceleration of Eq. (87): a_sigma = -G sum_i w_i rho_sigma'(r + c_i) c_i.
 // nb(i, s) returns rho_s at r + c_i.  Summation order is fixed (velocity
@@ -232,11 +253,6 @@ struct SiteNormals {
 
     __device__ __forceinline__ void stage1(const Phys<Real> &ph, const Counter &ctr, Real (&z)[K1])
     {
-        if (!ph.noisy) {
-#pragma unroll
-            for (int k = 0; k < K1; ++k) z[k] = 0;
-            return;
-        }
 #pragma unroll
         for (int b = 0; b < B1; ++b) {
             uint32_t w[4];
@@ -254,11 +270,6 @@ struct SiteNormals {
 
     __device__ __forceinline__ void stage2(const Phys<Real> &ph, const Counter &ctr, Real (&z)[K2])
     {
-        if (!ph.noisy) {
-#pragma unroll
-            for (int k = 0; k < K2; ++k) z[k] = 0;
-            return;
-        }
         auto put = [&](int word, uint32_t w) {
             Real a, c;
             word_normals<Real>(w, a, c);
@@ -303,14 +314,33 @@ __device__ __forceinline__ SiteCommon<Real> site_common(const Real (&rho)[2], co
     const Real rt = rho[0] + rho[1];
     c.u[0] = c.u[1] = c.u[2] = 0;
     if (rt > Real(0)) {
-        const Real inv_rt = Real(1) / rt;
+        const Real inv_rt = rcp(rt);
 #pragma unroll
         for (int al = 0; al < D; ++al)
             c.u[al] = (j[0][al] + j[1][al]) * inv_rt + Real(0.5) * ((c.F[0][al] + c.F[1][al]) * inv_rt);
     }
     c.sd = 0;
-    if (rho[0] > Real(0) && rho[1] > Real(0)) c.sd = ph.sd_gain * sqrt(rho[0] * rho[1] / rt);
+    if (rho[0] > Real(0) && rho[1] > Real(0)) c.sd = ph.sd_gain * root(rho[0] * rho[1] * rcp(rt));
     return c;
+}
+
+// base + w_i x.  In FP32 the weights 4/9, 1/9, 1/36 (D2Q9) and 1/3, 1/18,
+// 1/36 (D3Q19) round up, so their rounded values sum to 1 + 7e-9 (D2Q9) or
+// 1 + 1.5e-8 (D3Q19); with a plain product that excess would add
+// lambda * 1.5e-8 of the mass every step (a 3 % drift over 2e6 steps).  The
+// weight is applied as a head and a tail (w = w_hi + w_lo exactly to FP32
+// working precision), so the product carries only unbiased rounding.
+template <class L, class Real>
+__device__ __forceinline__ Real relax_add(int i, Real base, Real x)
+{
+    const double wd = (double)L::w36[i] / 36.0;
+    if constexpr (sizeof(Real) == 4) {
+        const float hi = (float)wd;
+        const float lo = (float)(wd - (double)hi);
+        return __builtin_fmaf(x, hi, __builtin_fmaf(x, lo, base));
+    } else {
+        return base + wd * x;
+    }
 }
 
 // Collision of species s at one site, in place.  zmom: the D momentum
@@ -329,14 +359,14 @@ __device__ __forceinline__ void collide_species(int s, Real (&f)[L::Q], Real r, 
         R[al] = ph.lam_d * (r * c.u[al] - js[al]) + (Real(1) - Real(0.5) * ph.lam_d) * c.F[s][al] +
                 sgn_sd * zmom[al];
     if (r > Real(0)) {
-        const Real inv_r = Real(1) / r;
+        const Real inv_r = rcp(r);
 #pragma unroll
         for (int al = 0; al < D; ++al) v[al] = (js[al] + Real(0.5) * R[al]) * inv_r;
     }
 
     // non-hydrodynamic mode noise, zs[a] = g z_a / sqrt(N_a)
     Real zs[Q];
-    const Real g = r > Real(0) ? ph.gain[s] * sqrt(r) : Real(0);
+    const Real g = r > Real(0) ? ph.gain[s] * root(r) : Real(0);
 #pragma unroll
     for (int q = 0; q < Q; ++q) zs[q] = 0;
 #pragma unroll
@@ -374,9 +404,8 @@ __device__ __forceinline__ void collide_species(int s, Real (&f)[L::Q], Real r, 
         if (D == 3 && cy && cz) cMc += (cy * cz > 0) ? Myz2 : -Myz2;
         if (D == 3 && cx && cz) cMc += (cx * cz > 0) ? Mxz2 : -Mxz2;
         const Real E = A + cMc + mn.even(i);
-        const Real w = Real(L::w36[i]) / Real(36);
         if (ib == i) {
-            f[i] = keep * f[i] + w * E;
+            f[i] = relax_add<L>(i, keep * f[i], E);
             continue;
         }
         Real cV = 0;
@@ -384,8 +413,8 @@ __device__ __forceinline__ void collide_species(int s, Real (&f)[L::Q], Real r, 
         if (cy) cV += cy > 0 ? Vy : -Vy;
         if (D == 3 && cz) cV += cz > 0 ? Vz : -Vz;
         const Real O = cV + mn.odd(i);
-        f[i] = keep * f[i] + w * (E + O);
-        f[ib] = keep * f[ib] + w * (E - O);
+        f[i] = relax_add<L>(i, keep * f[i], E + O);
+        f[ib] = relax_add<L>(ib, keep * f[ib], E - O);
     }
 }
 

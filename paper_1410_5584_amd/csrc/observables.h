@@ -110,7 +110,7 @@ __global__ __launch_bounds__(kRedBlock) void sums_kernel(const S *src, double *p
 
 // Fixed-order final reduction: out[k] = sum over blocks of partial[b][k];
 // if accum != nullptr, accum[k] += that sum instead.
-__global__ __launch_bounds__(kRedBlock) void finalize_kernel(const double *partial, int nblocks, int nv,
+static __global__ __launch_bounds__(kRedBlock) void finalize_kernel(const double *partial, int nblocks, int nv,
                                                              double *out, double *accum)
 {
     __shared__ double sh[kRedBlock];
@@ -265,7 +265,7 @@ __global__ __launch_bounds__(256) void sk_field_kernel(const S *src, const typen
 // sum against an LDS twiddle table.  L <= 2048.
 constexpr int kMaxLine = 2048;
 
-__global__ __launch_bounds__(256) void dft_lines_kernel(double2 *A, int L, size_t stride, int inner,
+static __global__ __launch_bounds__(256) void dft_lines_kernel(double2 *A, int L, size_t stride, int inner,
                                                         size_t inner_stride, size_t outer_stride)
 {
     extern __shared__ double2 lds[];  // 2 * L (data, ping-pong / twiddles)
@@ -320,7 +320,7 @@ __global__ __launch_bounds__(256) void dft_lines_kernel(double2 *A, int L, size_
 
 // acc[t] += scale * Re(A conj(B)) (B = A for an auto spectrum); k = 0 (the
 // mean, removed by the definition dX = X - <X>) is skipped.
-__global__ __launch_bounds__(256) void sk_accum_kernel(const double2 *A, const double2 *B, double *acc,
+static __global__ __launch_bounds__(256) void sk_accum_kernel(const double2 *A, const double2 *B, double *acc,
                                                        size_t n, double scale)
 {
     for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
@@ -330,7 +330,7 @@ __global__ __launch_bounds__(256) void sk_accum_kernel(const double2 *A, const d
     }
 }
 
-__global__ __launch_bounds__(256) void fill_kernel(double *p, size_t n, double v)
+static __global__ __launch_bounds__(256) void fill_kernel(double *p, size_t n, double v)
 {
     for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) p[t] = v;
 }

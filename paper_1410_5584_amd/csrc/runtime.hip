@@ -14,9 +14,12 @@
 
 using namespace fmlb;
 
-namespace {
-
+namespace fmlb {
+// Last HIP error of any entry point (shared with the batched entry points).
 thread_local int32_t g_last_hip = 0;
+}  // namespace fmlb
+
+namespace {
 
 #define HIP_TRY(...)                                   \
     do {                                               \
@@ -165,12 +168,15 @@ Phys<Real> make_phys(const fmlb_params &p)
     ph.lam[1] = (Real)lam1;
     ph.lam_d = (Real)lam_d;
     ph.negG = (Real)(-p.G);
-    ph.gain[0] = (Real)std::sqrt((2.0 * lam0 - lam0 * lam0) * mu);
-    ph.gain[1] = (Real)std::sqrt((2.0 * lam1 - lam1 * lam1) * mu);
-    ph.sd_gain = (p.flags & FMLB_NOISE_NO_SDF) ? (Real)0 : (Real)std::sqrt((2.0 * lam_d - lam_d * lam_d) * p.kT);
+    // Without noise every amplitude is zero: the normals are still drawn
+    // (the kernels carry no noise-off branch) and contribute exact zeros.
+    const bool noisy = (p.kT > 0.0) && !(p.flags & FMLB_NOISE_OFF);
+    const bool sdf = noisy && !(p.flags & FMLB_NOISE_NO_SDF);
+    ph.gain[0] = noisy ? (Real)std::sqrt((2.0 * lam0 - lam0 * lam0) * mu) : (Real)0;
+    ph.gain[1] = noisy ? (Real)std::sqrt((2.0 * lam1 - lam1 * lam1) * mu) : (Real)0;
+    ph.sd_gain = sdf ? (Real)std::sqrt((2.0 * lam_d - lam_d * lam_d) * p.kT) : (Real)0;
     ph.key0 = (uint32_t)p.seed;
     ph.key1 = (uint32_t)(p.seed >> 32);
-    ph.noisy = (p.kT > 0.0) && !(p.flags & FMLB_NOISE_OFF);
     return ph;
 }
 

@@ -73,3 +73,34 @@ def test_null_and_alignment_errors(fm):
         fm.fmlb_create(p.c(), 0, [256 + 8, 512, 768])
     assert e.value.status == fm.FMLB_E_INVALID
     assert fm.lib().fmlb_status_string(fm.FMLB_E_STATE).decode() == "populations not initialised"
+
+
+def _rep(fm, **kw):
+    d = dict(lattice="d2q9", storage="f32", nx=40, ny=33, kT=1e-5, G=0.3)
+    d.update(kw)
+    return fm.Params(**d).c()
+
+
+def test_batch_required_bytes(fm):
+    reps = [_rep(fm, nx=40, ny=33), _rep(fm, nx=256, ny=256), _rep(fm, nx=1, ny=1)]
+    a = fm.fmlb_batch_required_bytes(reps, 0)
+    # each replica block 2 x 9 x sites floats, rounded up to 256 bytes
+    want = sum(((2 * 9 * n * 4 + 255) // 256) * 256 for n in (40 * 33, 256 * 256, 1))
+    assert a == want
+    assert fm.fmlb_batch_required_bytes(reps, 1) == want
+    assert fm.fmlb_batch_required_bytes(reps, 2) > 2 * 256 * 256 * 8
+
+
+@pytest.mark.parametrize("bad", [
+    dict(lattice="d3q19", nz=4), dict(storage="f64"), dict(storage="bf16"), dict(nz=2),
+    dict(tau=(0.5, 1.0)), dict(kT=-1.0), dict(nx=0),
+])
+def test_batch_invalid_replica_rejected(fm, bad):
+    reps = [_rep(fm), _rep(fm, **bad)]
+    assert fm.fmlb_batch_required_bytes(reps, 0) == 0
+    with pytest.raises(fm.FmlbError) as e:
+        fm.fmlb_batch_create(reps, 0, [256, 512, 768])
+    assert e.value.status == fm.FMLB_E_INVALID
+    with pytest.raises(fm.FmlbError) as e:
+        fm.fmlb_batch_create([_rep(fm)], 0, [256, 0, 768])
+    assert e.value.status == fm.FMLB_E_NULL
