@@ -1,16 +1,26 @@
 """Benchmark of the fused two-species FLBE step on one MI355X.
 
-Workload (the headline configuration): D3Q19, 256^3 periodic sites, two
-species, FP32 storage and arithmetic, G = 1.2, tau = tau_d = 1, k_BT = 1e-5,
-initial densities 1 + U(-0.01, 0.01) per species and site (seed 1), thermal
-noise on.  A step is one full pass of the hot path (pull streaming, moments,
-lattice force from the neighbours' densities, counter-based noise, collision,
-store) over every site.  The metric is MLUPS: million two-species site
-updates per second, with the populations resident in HBM.
+Headline workload: D3Q19, 256^3 periodic sites, two species, FP32 storage and
+arithmetic, G = 1.2, tau = tau_d = 1, k_BT = 1e-5, initial densities
+1 + U(-0.01, 0.01) per species and site (seed 1), thermal noise on.  A step is
+one full pass of the hot path (pull streaming, moments, lattice force from the
+neighbours' densities, counter-based noise, collision, store) over every
+site; it is one launch of the fused step kernel, so the per-step time is that
+kernel's average launch duration.  The metric is MLUPS (million two-species
+site updates per second) with the populations resident in HBM.
 
-Prints one JSON line.  Also reports the roofline of the step kernel (HBM
-bound: algorithmic bytes = read + write of 2 Q populations per site) and the
-FP64 CPU oracle timed on a bounded sample of the same workload.
+Prints one JSON line with the headline value, the roofline of the step kernel
+(HBM bound; algorithmic bytes = read + write of 2 Q populations per site), the
+same step with 16-bit deviation storage, the D2Q9 1024^2 lattice, the 512
+batched D2Q9 replicas against one launch per replica, and the FP64 CPU oracle
+timed on a bounded sample of the headline workload.
+
+Helper modes for the rocprofv3 traffic figure:
+  --copy-calibration   one plain 2 GiB device copy (known bytes), to scale the
+                       FETCH_SIZE / WRITE_SIZE counters;
+  --traffic-json F W CF CW   turn the four counter databases (step FETCH,
+                       step WRITE, copy FETCH, copy WRITE) into
+                       profiles/fused_step_d3q19_f32_256cube_traffic.json.
 """
 from __future__ import annotations
 
@@ -18,6 +28,7 @@ import argparse
 import hashlib
 import json
 import os
+import sqlite3
 import sys
 import time
 
@@ -27,9 +38,14 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 WORKLOAD = dict(lattice="d3q19", nx=256, ny=256, nz=256, tau=(1.0, 1.0), tau_d=1.0, G=1.2, kT=1e-5, seed=1)
+C1 = dict(lattice="d2q9", nx=1024, ny=1024, nz=1, tau=(0.8, 1.2), tau_d=1.0, G=0.5, kT=1e-5, seed=1)
 BYTES_PER_SITE = {("d3q19", "f32"): 304, ("d3q19", "bf16"): 152, ("d3q19", "f16"): 152,
                   ("d2q9", "f32"): 144, ("d2q9", "f64"): 288}
 KERNEL_SOURCES = ["collide.h", "rng.h", "fused.h", "kernels.h", "storage.h", "lattice.h"]
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "fused_step_d3q19_f32_256cube_traffic.json")
+COPY_BYTES = 2 ** 31
+STEP_KERNEL = "fused_step_kernel<fmlb::D3Q19, float"
+COPY_KERNEL = "copyBuffer"
 
 
 def kernel_hash() -> str:
@@ -43,9 +59,8 @@ def kernel_hash() -> str:
 def measured_traffic():
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel sources (else None)."""
-    path = os.path.join(ROOT, "profiles", "fused_step_d3q19_f32_256cube_traffic.json")
     try:
-        with open(path) as fh:
+        with open(TRAFFIC_JSON) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
@@ -54,9 +69,54 @@ def measured_traffic():
     return rec.get("bytes_per_launch")
 
 
-def time_steps(fm, torch, storage: str, steps: int, warmup: int):
+def _counter_mean(db: str, counter: str, kernel_part: str) -> float:
+    con = sqlite3.connect(db)
+    vals = [v for k, c, v in con.execute("select kernel_name, counter_name, value from counters_collection")
+            if c == counter and kernel_part in k]
+    if not vals:
+        raise SystemExit(f"{db}: no {counter} for a kernel matching {kernel_part!r}")
+    return sum(vals) / len(vals)
+
+
+def write_traffic_json(fetch_db: str, write_db: str, cfetch_db: str, cwrite_db: str) -> dict:
+    f = _counter_mean(fetch_db, "FETCH_SIZE", STEP_KERNEL)
+    w = _counter_mean(write_db, "WRITE_SIZE", STEP_KERNEL)
+    cf = _counter_mean(cfetch_db, "FETCH_SIZE", COPY_KERNEL)
+    cw = _counter_mean(cwrite_db, "WRITE_SIZE", COPY_KERNEL)
+    kf, kw = COPY_BYTES / (cf * 1024.0), COPY_BYTES / (cw * 1024.0)
+    read_b, write_b = f * 1024.0 * kf, w * 1024.0 * kw
+    sites = WORKLOAD["nx"] * WORKLOAD["ny"] * WORKLOAD["nz"]
+    rec = {"kernel": "fused_step_kernel<D3Q19, float, 64, 8, async>", "workload": "D3Q19 256^3 FP32",
+           "kernel_hash": kernel_hash(), "fetch_kib_per_launch": f, "write_kib_per_launch": w,
+           "copy_calibration": {"bytes": COPY_BYTES, "fetch_kib": cf, "write_kib": cw,
+                                "fetch_scale": kf, "write_scale": kw},
+           "read_bytes_per_launch": read_b, "write_bytes_per_launch": write_b,
+           "bytes_per_launch": read_b + write_b,
+           "algorithmic_bytes_per_launch": BYTES_PER_SITE[("d3q19", "f32")] * sites}
+    os.makedirs(os.path.dirname(TRAFFIC_JSON), exist_ok=True)
+    with open(TRAFFIC_JSON, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    return rec
+
+
+def copy_calibration():
+    import torch
+    torch.cuda.set_device(0)
+    a = torch.ones(COPY_BYTES // 4, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": COPY_BYTES, "copies": 3}), flush=True)
+
+
+def _events(torch):
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def time_steps(fm, torch, storage: str, steps: int, warmup: int, work=WORKLOAD):
     import workloads
-    p = fm.Params(storage=storage, rho_ref=(1.0, 1.0), **WORKLOAD)
+    p = fm.Params(storage=storage, rho_ref=(1.0, 1.0), **work)
     lat = fm.Lattice(p)
     shape = (p.nz, p.ny, p.nx)
     r1, r2 = workloads.initial_density(shape, "perturbed", seed=p.seed, amplitude=0.01)
@@ -64,8 +124,7 @@ def time_steps(fm, torch, storage: str, steps: int, warmup: int):
     del r1, r2
     lat.step(warmup)
     stream = lat.stream
-    start = torch.cuda.Event(enable_timing=True)
-    end = torch.cuda.Event(enable_timing=True)
+    start, end = _events(torch)
     torch.cuda.synchronize()
     start.record(stream)
     lat.step(steps)
@@ -75,11 +134,62 @@ def time_steps(fm, torch, storage: str, steps: int, warmup: int):
     sums = lat.global_sums()
     health = lat.health()
     lat.close()
-    return ms, lat.nsites, sums, health
+    return ms, p.nx * p.ny * p.nz, sums, health
 
 
-def cpu_baseline():
-    """The FP64 oracle (as it stands) on one step of the full 256^3 workload."""
+def batched(fm, torch, steps: int, warmup: int, plain_steps: int):
+    """512 D2Q9 FP32 replicas (log-uniform sizes 32^2..256^2, per-replica
+    seed, k_BT, G): one launch per step from replayed HIP graphs with the
+    autotuned work list, against one launch per replica per step."""
+    import workloads
+    reps = workloads.replica_table(512)
+    ps = [fm.Params(lattice="d2q9", storage="f32", nx=r["L"], ny=r["L"], nz=1, tau=r["tau"], tau_d=r["tau_d"],
+                    G=r["G"], kT=r["kT"], seed=r["seed"]) for r in reps]
+    sites = sum(p.nx * p.ny for p in ps)
+    b = fm.Batch(ps)
+    for r in range(len(ps)):
+        b.init_density(r, 1.0, 1.0)
+    tile = b.autotune(reps=5)
+    b.step(max(warmup, 32), use_graph=True)
+    steps = max(32, (steps // 32) * 32)
+    start, end = _events(torch)
+    torch.cuda.synchronize()
+    start.record(b.stream)
+    b.step(steps, use_graph=True)
+    end.record(b.stream)
+    torch.cuda.synchronize()
+    ms_b = start.elapsed_time(end) / steps
+    b.close()
+    lats = []
+    for p in ps:
+        lat = fm.Lattice(p)
+        lat.init_density(1.0, 1.0)
+        lats.append(lat)
+    for lat in lats:
+        lat.step(2)
+    start, end = _events(torch)
+    torch.cuda.synchronize()
+    start.record(lats[0].stream)
+    for _ in range(plain_steps):
+        for lat in lats:
+            lat.step(1)
+    end.record(lats[0].stream)
+    torch.cuda.synchronize()
+    ms_p = start.elapsed_time(end) / plain_steps
+    for lat in lats:
+        lat.close()
+    mlups_b, mlups_p = sites / ms_b / 1e3, sites / ms_p / 1e3
+    return {"value": round(mlups_b, 2), "unit": "MLUPS", "ms_per_step": round(ms_b, 4), "sites": sites,
+            "replicas": len(ps), "tile": list(tile), "graph_steps": 32,
+            "hbm_frac": round(BYTES_PER_SITE[("d2q9", "f32")] * sites / (ms_b / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            "plain_per_replica": {"value": round(mlups_p, 2), "unit": "MLUPS", "ms_per_step": round(ms_p, 4),
+                                  "steps": plain_steps},
+            "vs_plain": round(mlups_b / mlups_p, 2),
+            "note": "sites fit in the 256 MB last-level cache: HBM fraction is nominal"}
+
+
+def cpu_baseline(steps: int = 5):
+    """The FP64 oracle (as it stands) on `steps` steps of the full 256^3 workload."""
     import numpy as np
 
     import oracle
@@ -91,13 +201,13 @@ def cpu_baseline():
     r1, r2 = workloads.initial_density(shape, "perturbed", seed=WORKLOAD["seed"], amplitude=0.01)
     s.init_density(r1, r2)
     del r1, r2
-    steps = 1
     t0 = time.perf_counter()
     s.step(steps)
     dt = time.perf_counter() - t0
     n = int(np.prod(shape))
-    return {"value": n * steps / dt / 1e6, "unit": "MLUPS", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{steps} step of the full 256^3 D3Q19 workload in FP64 ({dt:.1f} s)"}
+    return {"value": round(n * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{steps} steps of the full 256^3 D3Q19 workload in FP64 ({dt:.1f} s)"}
 
 
 def main() -> int:
@@ -107,11 +217,19 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--traffic-json", nargs=4, metavar=("FETCH_DB", "WRITE_DB", "COPY_FETCH_DB", "COPY_WRITE_DB"))
     args = ap.parse_args()
+    if args.traffic_json:
+        print(json.dumps(write_traffic_json(*args.traffic_json)), flush=True)
+        return 0
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU slab "
               "decomposition is a design, not built", file=sys.stderr)
         return 2
+    if args.copy_calibration:
+        copy_calibration()
+        return 0
 
     import torch
 
@@ -133,8 +251,9 @@ def main() -> int:
         "config": {"workload": "D3Q19 256^3 periodic, two species, FP32, G=1.2, tau=1, k_BT=1e-5, "
                                "rho=1+U(-0.01,0.01), seed 1", "sites": nsites, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "algorithmic_bytes_per_site": bps},
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None if traffic is None else round(traffic),
+                     "algorithmic_bytes_per_launch": bps * nsites},
         "checks": {"mass": [float(sums[0]), float(sums[1])], "health": list(health)},
     }
     if not args.no_variants:
@@ -142,9 +261,16 @@ def main() -> int:
         for storage in ("bf16", "f16"):
             ms16, _, _, h16 = time_steps(fm, torch, storage, args.steps, args.warmup)
             m16 = nsites * args.steps / (ms16 / 1e3) / 1e6
-            var[f"{storage}_dev"] = {"value": round(m16, 2), "unit": "MLUPS", "vs_f32": round(m16 / mlups, 3),
-                                     "hbm_frac": round(BYTES_PER_SITE[("d3q19", storage)] * nsites /
-                                                       (ms16 / args.steps / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+            var[f"d3q19_256cube_{storage}_dev"] = {
+                "value": round(m16, 2), "unit": "MLUPS", "ms_per_step": round(ms16 / args.steps, 4),
+                "vs_f32": round(m16 / mlups, 3),
+                "hbm_frac": round(BYTES_PER_SITE[("d3q19", storage)] * nsites / (ms16 / args.steps / 1e3) / 1e9
+                                  / HBM_PEAK_GBS, 4)}
+        ms1, n1, _, _ = time_steps(fm, torch, "f32", args.steps, args.warmup, work=C1)
+        var["d2q9_1024sq_f32"] = {"value": round(n1 * args.steps / (ms1 / 1e3) / 1e6, 2), "unit": "MLUPS",
+                                  "ms_per_step": round(ms1 / args.steps, 4),
+                                  "note": "75 MB per buffer, cache-resident: HBM fraction not meaningful"}
+        var["d2q9_512_replicas_batched_f32"] = batched(fm, torch, args.steps, args.warmup, plain_steps=10)
         rec["variants"] = var
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline()

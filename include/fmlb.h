@@ -262,6 +262,14 @@ fmlb_status fmlb_batch_step(fmlb_batch *b, int64_t n, int use_graph);
  * not depend on it.  Discards a captured graph. */
 fmlb_status fmlb_batch_set_tile(fmlb_batch *b, int tile_x, int march);
 
+/* Tile autotuner: times every supported work-list shape (tile_x 64, 128,
+ * 256 x march 4, 8, 16, 32, 64) over `reps` recomputations of the next step
+ * (the state and the step counter are left unchanged: each trial re-reads
+ * the current state and overwrites the other buffer), keeps the fastest and
+ * reports it.  Synchronises.  FMLB_E_STATE until every replica is
+ * initialised; FMLB_E_INVALID for reps outside [1, 1000]. */
+fmlb_status fmlb_batch_autotune(fmlb_batch *b, int reps, int *tile_x, int *march);
+
 /* As fmlb_get_populations, for replica r.  Synchronises. */
 fmlb_status fmlb_batch_get_populations(fmlb_batch *b, int r, double *host, size_t bytes);
 

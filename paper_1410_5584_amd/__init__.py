@@ -89,6 +89,8 @@ _SIGNATURES = {
     "fmlb_batch_mode_accumulate": (ctypes.c_int32, [_vp]),
     "fmlb_batch_mode_variances": (ctypes.c_int32, [_vp, ctypes.c_int, _dp, _i64p]),
     "fmlb_batch_reset_modes": (ctypes.c_int32, [_vp]),
+    "fmlb_batch_autotune": (ctypes.c_int32, [_vp, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                             ctypes.POINTER(ctypes.c_int)]),
     "fmlb_batch_set_tile": (ctypes.c_int32, [_vp, ctypes.c_int, ctypes.c_int]),
     "fmlb_batch_size": (ctypes.c_int, [_vp]),
     "fmlb_batch_total_sites": (ctypes.c_int64, [_vp]),
@@ -275,6 +277,12 @@ def fmlb_batch_step(b: int, n: int, use_graph: bool):
 
 def fmlb_batch_set_tile(b: int, tile_x: int, march: int):
     _check("fmlb_batch_set_tile", lib().fmlb_batch_set_tile(_vp(b), tile_x, march))
+
+
+def fmlb_batch_autotune(b: int, reps: int):
+    tx, ch = ctypes.c_int(), ctypes.c_int()
+    _check("fmlb_batch_autotune", lib().fmlb_batch_autotune(_vp(b), reps, ctypes.byref(tx), ctypes.byref(ch)))
+    return tx.value, ch.value
 
 
 def fmlb_batch_get_populations(b: int, r: int, out: np.ndarray):
@@ -476,6 +484,10 @@ class Batch:
 
     def set_tile(self, tile_x: int = 0, march: int = 0):
         fmlb_batch_set_tile(self.b, tile_x, march)
+
+    def autotune(self, reps: int = 10):
+        """Pick the fastest work-list shape; returns (tile_x, march)."""
+        return fmlb_batch_autotune(self.b, reps)
 
     def populations(self, r: int):
         out = np.empty((2, 9, 1) + self.shape(r))

@@ -431,6 +431,53 @@ fmlb_status fmlb_batch_set_tile(fmlb_batch *b, int tile_x, int chunk)
     return build_items(b, tx, ch);
 }
 
+fmlb_status fmlb_batch_autotune(fmlb_batch *b, int reps, int *tile_x, int *march)
+{
+    if (!b) return FMLB_E_NULL;
+    if (reps < 1 || reps > 1000) return FMLB_E_INVALID;
+    for (char rd : b->ready)
+        if (!rd) return FMLB_E_STATE;
+    static const int kTiles[] = {64, 128, 256};
+    static const int kMarch[] = {4, 8, 16, 32, 64};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    BATCH_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return FMLB_E_HIP;
+    }
+    float best = 1e30f;
+    int btx = b->tile_x, bch = b->chunk;
+    fmlb_status st = FMLB_OK;
+    for (int tx : kTiles) {
+        for (int ch : kMarch) {
+            if ((st = build_items(b, tx, ch))) break;
+            // Step n -> n+1 recomputed `reps` times: the state of step n is
+            // only read, the counter is not advanced, so the run is invisible.
+            for (int w = 0; w < 2 && !st; ++w) st = launch_batch_step(b, 0, b->stream);
+            if (!st && hipEventRecord(e0, b->stream) != hipSuccess) st = FMLB_E_HIP;
+            for (int k = 0; k < reps && !st; ++k) st = launch_batch_step(b, 0, b->stream);
+            if (!st && hipEventRecord(e1, b->stream) != hipSuccess) st = FMLB_E_HIP;
+            if (!st && hipEventSynchronize(e1) != hipSuccess) st = FMLB_E_HIP;
+            float ms = 0;
+            if (!st && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = FMLB_E_HIP;
+            if (st) break;
+            if (ms < best) {
+                best = ms;
+                btx = tx;
+                bch = ch;
+            }
+        }
+        if (st) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st) return st;
+    if ((st = build_items(b, btx, bch))) return st;
+    if (tile_x) *tile_x = btx;
+    if (march) *march = bch;
+    return FMLB_OK;
+}
+
 fmlb_status fmlb_batch_get_populations(fmlb_batch *b, int r, double *host, size_t bytes)
 {
     if (!b || !host) return FMLB_E_NULL;

@@ -181,3 +181,23 @@ def test_batch_rejects_step_before_init(fm):
         b.set_tile(96, 4)
     assert e.value.status == fm.FMLB_E_INVALID
     b.close()
+
+
+def test_batch_autotune_leaves_state_and_results_unchanged(fm):
+    _say("case batch autotune")
+    b0, _ = _batch(fm)
+    b1, _ = _batch(fm)
+    b0.step(4)
+    b1.step(4)
+    before = [b1.populations(r) for r in range(len(REPLICAS))]
+    tx, march = b1.autotune(reps=2)
+    assert tx in (64, 128, 256) and march in (4, 8, 16, 32, 64)
+    assert b1.step_count == 4
+    for r in range(len(REPLICAS)):
+        assert np.array_equal(b1.populations(r), before[r]), r
+    b0.step(5)
+    b1.step(5, use_graph=True)
+    for r in range(len(REPLICAS)):
+        assert np.array_equal(b0.populations(r), b1.populations(r)), r
+    b0.close()
+    b1.close()
