@@ -151,6 +151,32 @@ class LinearFLBE:
         out["vbvb"] = np.mean([s(f"vb_{a}", f"vb_{a}") for a in range(self.D)])
         return out
 
+    def mode_variance_ratios(self, T, N, L=13):
+        """Stationary <m_a^2> / (N_a mu rho0_s) of the pre-collision modes
+        m_a = sum_i T_ai f_i of each species ([2][Q]), averaged over the
+        wavevectors of an L^D grid with k = 0 left out: the equipartition
+        check of Sec. VI A including the corrections the mean-field force
+        brings at G > 0 (exactly 1 at G = 0).  L is odd so that no grid point
+        has a component pi, where some lattice modes do not relax and the
+        stationary covariance is undefined.  T's columns follow this module's
+        velocity order."""
+        if L % 2 == 0:
+            raise ValueError("use an odd grid size")
+        Q, D = self.Q, self.D
+        ks = 2 * np.pi * np.fft.fftfreq(L)
+        grid = np.stack(np.meshgrid(*([ks] * D), indexing="ij"), -1).reshape(-1, D)
+        acc = np.zeros((2, Q))
+        cnt = 0
+        for k in grid:
+            if not np.any(k):
+                continue
+            S = self.covariance(k)
+            for s in range(2):
+                blk = S[s * Q:(s + 1) * Q, s * Q:(s + 1) * Q]
+                acc[s] += np.real(np.einsum("ai,ij,aj->a", T, blk, T))
+            cnt += 1
+        return acc / cnt / (np.asarray(N)[None, :] * 3.0 * self.kT * self.rho0[:, None])
+
     def spectral_radius(self, k):
         M, _ = self.operators(k)
         return np.max(np.abs(np.linalg.eigvals(M)))
