@@ -69,24 +69,24 @@ def measured_traffic():
     return rec.get("bytes_per_launch")
 
 
-def _counter_mean(db: str, counter: str, kernel_part: str) -> float:
+def _counter_mean(db: str, counter: str, kernel_part: str):
     con = sqlite3.connect(db)
-    vals = [v for k, c, v in con.execute("select kernel_name, counter_name, value from counters_collection")
+    rows = [(k, v) for k, c, v in con.execute("select kernel_name, counter_name, value from counters_collection")
             if c == counter and kernel_part in k]
-    if not vals:
+    if not rows:
         raise SystemExit(f"{db}: no {counter} for a kernel matching {kernel_part!r}")
-    return sum(vals) / len(vals)
+    return sum(v for _, v in rows) / len(rows), rows[0][0], len(rows)
 
 
 def write_traffic_json(fetch_db: str, write_db: str, cfetch_db: str, cwrite_db: str) -> dict:
-    f = _counter_mean(fetch_db, "FETCH_SIZE", STEP_KERNEL)
-    w = _counter_mean(write_db, "WRITE_SIZE", STEP_KERNEL)
-    cf = _counter_mean(cfetch_db, "FETCH_SIZE", COPY_KERNEL)
-    cw = _counter_mean(cwrite_db, "WRITE_SIZE", COPY_KERNEL)
+    f, kname, launches = _counter_mean(fetch_db, "FETCH_SIZE", STEP_KERNEL)
+    w, _, _ = _counter_mean(write_db, "WRITE_SIZE", STEP_KERNEL)
+    cf, _, _ = _counter_mean(cfetch_db, "FETCH_SIZE", COPY_KERNEL)
+    cw, _, _ = _counter_mean(cwrite_db, "WRITE_SIZE", COPY_KERNEL)
     kf, kw = COPY_BYTES / (cf * 1024.0), COPY_BYTES / (cw * 1024.0)
     read_b, write_b = f * 1024.0 * kf, w * 1024.0 * kw
     sites = WORKLOAD["nx"] * WORKLOAD["ny"] * WORKLOAD["nz"]
-    rec = {"kernel": "fused_step_kernel<D3Q19, float, 64, 8, async>", "workload": "D3Q19 256^3 FP32",
+    rec = {"kernel": kname, "workload": "D3Q19 256^3 FP32", "launches": launches,
            "kernel_hash": kernel_hash(), "fetch_kib_per_launch": f, "write_kib_per_launch": w,
            "copy_calibration": {"bytes": COPY_BYTES, "fetch_kib": cf, "write_kib": cw,
                                 "fetch_scale": kf, "write_scale": kw},

@@ -202,7 +202,8 @@ fmlb_status fmlb_health(fmlb_ctx *ctx, int64_t counts[2]);
 /* Launch shape of the fused step: tile of tile_x x tile_y sites per
  * workgroup in the plane orthogonal to the march axis (z for D3Q19, y for
  * D2Q9, where tile_y must be 1) and `march` planes walked per workgroup.
- * Supported tiles: D3Q19 64x4, 64x8, 32x8, 32x16; D2Q9 64x1, 128x1, 256x1.
+ * Supported tiles: D3Q19 256x2 (full-width rows: only for nx = 256), 128x4,
+ * 64x4, 64x8, 32x8, 32x16; D2Q9 64x1, 128x1, 256x1; march 1..4096.
  * 0 = default for each argument.  tile_x = 1 selects the two-pass form (a
  * density pass, then the step).  Results do not depend on the choice (same
  * bits).  FMLB_E_INVALID for an unsupported shape. */

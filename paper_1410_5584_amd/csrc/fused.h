@@ -538,6 +538,218 @@ __device__ __forceinline__ void fused_tile_async(const StepArgs<L, S> &a, int t0
     }
 }
 
+// ---------------------------------------------------------------------------
+// Full-width tiles (D3Q19, tile width = nx): every row of the tile is a whole
+// lattice row, so each population is read as contiguous nx-site rows and the
+// x halo is the tile's own periodic image (written into the ring's edge
+// columns, no loads).  The halo is then just the rows y0 - 1 and y0 + T1, one
+// site per thread; their populations are pulled into registers before the
+// collision (the LDS holds only the tile's own rows), which keeps the
+// workgroup's LDS within one CU.  Ordering as in fused_tile_async.
+// ---------------------------------------------------------------------------
+template <class L, class S, int T0, int T1>
+__device__ __forceinline__ void fused_tile_rows(const StepArgs<L, S> &a, int t0, int t1, int mbeg, int mend)
+{
+    using Real = typename Storage<S>::Real;
+    using Raw = uint32_t;
+    using A = MarchAxes<L>;
+    constexpr int Q = L::Q;
+    constexpr bool D3 = A::three_d;
+    constexpr int H0 = T0 + 2;
+    constexpr int H1 = D3 ? T1 + 2 : 1;
+    constexpr int OFF1 = D3 ? 1 : 0;
+    constexpr int PLANE = H0 * H1;
+    constexpr int NT = T0 * T1;
+    constexpr int NHALO = 2 * T0;  // rows y-1 and y+T1; the x halo is the tile's own periodic image
+    constexpr uint32_t ES = sizeof(S);
+    static_assert(D3 || T1 == 1, "2D tiles are one row");
+    static_assert(D3 && NHALO <= NT, "full-width tiles: D3Q19, at least two rows");
+    static_assert(NT % 64 == 0, "whole waves");
+
+    __shared__ Real ring[4][2][PLANE];
+    __shared__ Raw own[2 * Q][NT];      // plane m+1 (then m+2) populations of the tile
+
+    const Geom g = a.g;
+    const int n0 = g.nx, n1 = D3 ? g.ny : 1, nm = D3 ? g.nz : g.ny;
+    const uint32_t s1 = (uint32_t)n0;
+    const uint32_t sm = D3 ? (uint32_t)n0 * n1 : (uint32_t)n0;
+    const uint32_t pop_bytes = (uint32_t)g.nsites * ES;
+
+    __amdgpu_buffer_rsrc_t rsrc[2], rdst[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        rsrc[s] = __builtin_amdgcn_make_buffer_rsrc((void *)(a.src + (size_t)s * Q * g.nsites), 0,
+                                                    (int)(Q * pop_bytes), kBufferWord3);
+        rdst[s] = __builtin_amdgcn_make_buffer_rsrc((void *)(a.dst + (size_t)s * Q * g.nsites), 0,
+                                                    (int)(Q * pop_bytes), kBufferWord3);
+    }
+
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int l0 = tid % T0, l1 = tid / T0;
+    const int p0raw = t0 * T0 + l0, p1raw = t1 * T1 + l1;
+    const bool inside = p0raw < n0 && p1raw < n1;
+    const int p0 = p0raw % n0, p1 = p1raw % n1;
+    const int box_own = (l1 + OFF1) * H0 + (l0 + 1);
+
+    // halo: the two rows y0 - 1 and y0 + T1, one site per thread
+    const int hrow = tid / T0, hx = tid % T0;
+    const int hh1 = hrow == 0 ? 0 : H1 - 1;
+    const int hb = hh1 * H0 + hx + 1;
+    const int hp0 = hx;
+    const int hp1 = ((t1 * T1 - 1 + (hrow == 0 ? 0 : T1 + 1)) % n1 + n1) % n1;
+    // ring positions of the periodic x images (columns -1 and T0)
+    auto put_ring = [&](float *row_plane, int box, int lx, float v) {
+        row_plane[box] = v;
+        if (lx == 0) row_plane[box + T0] = v;
+        if (lx == T0 - 1) row_plane[box - T0] = v;
+    };
+
+    const Real ref[2] = {a.ref[0], a.ref[1]};
+    auto slot = [&](int m) { return (m - mbeg + 1) & 3; };
+    auto wrapm = [&](int m) { return m < 0 ? m + nm : (m >= nm ? m - nm : m); };
+    auto pull_off = [&](int q0, int q1, int m, int i) -> uint32_t {
+        const int x = wrap(q0, -A::c0(i), n0);
+        const int y = D3 ? wrap(q1, -A::c1(i), n1) : 0;
+        const int z = wrap(m, -A::cm(i), nm);
+        return ((uint32_t)x + s1 * (uint32_t)y + sm * (uint32_t)z) * ES;
+    };
+    // Register pull (prologue only).
+    auto pull = [&](int q0, int q1, int m, Real (&f)[2][Q]) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const uint32_t voff = pull_off(q0, q1, m, i);
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                Real v = BufIO<S>::load(rsrc[s], voff, (uint32_t)i * pop_bytes);
+                if (Storage<S>::deviation) v += Real(L::w36[i]) / Real(36) * ref[s];
+                f[s][i] = v;
+            }
+        }
+    };
+    // Asynchronous pull of plane m into rows [2Q][len]: this wave's 64-lane slice.
+    auto dma_pull = [&](int q0, int q1, int m, Raw *rows, int len) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const uint32_t voff = pull_off(q0, q1, m, i);
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                lds_void_t *dst = (lds_void_t *)(rows + (s * Q + i) * len + wave * 64);
+                if constexpr (ES == 4)
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc[s], dst, 4, voff, (uint32_t)i * pop_bytes, 0, 0);
+                else
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc[s], dst, 2, voff, (uint32_t)i * pop_bytes, 0, 0);
+            }
+        }
+    };
+    auto read_rows = [&](const Raw *rows, int len, int idx, Real (&f)[2][Q]) {
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                Real v = DmaWord<S>::decode(rows[(s * Q + i) * len + idx]);
+                if (Storage<S>::deviation) v += Real(L::w36[i]) / Real(36) * ref[s];
+                f[s][i] = v;
+            }
+    };
+
+    Real cur[2][Q], rc[2], jc[2][3];
+    // Prologue: densities of plane mbeg-1, populations and moments of plane
+    // mbeg (register pulls), then the asynchronous pull of plane mbeg+1.
+#pragma unroll 1
+    for (int m = mbeg - 1; m <= mbeg; ++m) {
+        Real r, j[3];
+        {
+            Real h[2][Q];
+            pull(hp0, hp1, wrapm(m), h);
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                moments<L, Real>(h[s], r, j);
+                put_ring(ring[slot(m)][s], hb, hx, r);
+            }
+        }
+        Real f[2][Q];
+        pull(p0, p1, wrapm(m), f);
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            moments<L, Real>(f[s], r, j);
+            put_ring(ring[slot(m)][s], box_own, l0, r);
+            if (m == mbeg) {
+                rc[s] = r;
+#pragma unroll
+                for (int al = 0; al < 3; ++al) jc[s][al] = j[al];
+#pragma unroll
+                for (int i = 0; i < Q; ++i) cur[s][i] = f[s][i];
+            }
+        }
+    }
+    dma_pull(p0, p1, wrapm(mbeg + 1), &own[0][0], NT);
+    Real hn[2][Q];
+    pull(hp0, hp1, wrapm(mbeg + 1), hn);
+
+#pragma unroll 1
+    for (int m = mbeg; m < mend; ++m) {
+        // Rows of plane m+1 have landed.
+        __builtin_amdgcn_s_waitcnt(kWaitVm0);
+        Real nxt[2][Q], rn[2], jn[2][3];
+        read_rows(&own[0][0], NT, tid, nxt);
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            moments<L, Real>(nxt[s], rn[s], jn[s]);
+            put_ring(ring[slot(m + 1)][s], box_own, l0, rn[s]);
+        }
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            Real r, j[3];
+            moments<L, Real>(hn[s], r, j);
+            put_ring(ring[slot(m + 1)][s], hb, hx, r);
+        }
+        // Workgroup barrier for the density ring only: the ring writes are
+        // complete once lgkmcnt drains (no row loads are in flight here).
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
+        __builtin_amdgcn_s_barrier();
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+
+        auto nb = [&](int i, int s) -> Real {
+            const int sl = slot(m + A::cm(i));
+            return ring[sl][s][box_own + A::c1(i) * H0 + A::c0(i)];
+        };
+        Real acc[2][3];
+        lattice_acceleration<L, Real>(nb, a.ph.negG, acc);
+        // Every LDS read of this iteration is done: start the row loads of
+        // plane m+2 (no LDS read may follow them before the next vmcnt(0)).
+        const bool more = m + 2 <= mend;
+        __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
+        __builtin_amdgcn_sched_barrier(0);
+        if (more) {
+            dma_pull(p0, p1, wrapm(m + 2), &own[0][0], NT);
+            pull(hp0, hp1, wrapm(m + 2), hn);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        const uint32_t site = (uint32_t)p0 + s1 * (uint32_t)(D3 ? p1 : 0) + sm * (uint32_t)m;
+        const uint32_t voff = site * ES;
+        collide_site<L, Real>(cur, rc, jc, acc, a.ph, Counter{site, a.step_lo, a.step_hi}, [&](int s, auto &fs) {
+            if (inside) {
+#pragma unroll
+                for (int i = 0; i < Q; ++i) {
+                    Real v = fs[i];
+                    if (Storage<S>::deviation) v -= Real(L::w36[i]) / Real(36) * ref[s];
+                    BufIO<S>::store(v, rdst[s], voff, (uint32_t)i * pop_bytes);
+                }
+            }
+        });
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            rc[s] = rn[s];
+#pragma unroll
+            for (int al = 0; al < 3; ++al) jc[s][al] = jn[s][al];
+#pragma unroll
+            for (int i = 0; i < Q; ++i) cur[s][i] = nxt[s][i];
+        }
+    }
+}
+
 template <class L, class S, int T0, int T1, bool ASYNC>
 __global__ __launch_bounds__(T0 *T1) void fused_step_kernel(StepArgs<L, S> a, int chunk)
 {
@@ -550,7 +762,9 @@ __global__ __launch_bounds__(T0 *T1) void fused_step_kernel(StepArgs<L, S> a, in
     const int t1 = (int)((logical / tiles0) % tiles1);
     const int ck = (int)(logical / ((unsigned)tiles0 * tiles1));
     const int mbeg = ck * chunk, mend = min(ck * chunk + chunk, nm);
-    if constexpr (ASYNC)
+    if constexpr (L::D == 3 && T0 == 256)
+        fused_tile_rows<L, S, T0, T1>(a, t0, t1, mbeg, mend);
+    else if constexpr (ASYNC)
         fused_tile_async<L, S, T0, T1>(a, t0, t1, mbeg, mend);
     else
         fused_tile<L, S, T0, T1>(a, t0, t1, mbeg, mend);
@@ -566,7 +780,8 @@ bool fused_shape_valid(int tile_x, int tile_y, int march)
     if (std::is_same<S, double>::value) return false;
     if (march < 0 || march > 4096) return false;
     if (L::D == 3)
-        return (tile_x == 64 && (tile_y == 4 || tile_y == 8)) || (tile_x == 32 && (tile_y == 8 || tile_y == 16));
+        return (tile_x == 256 && tile_y == 2) || (tile_x == 128 && tile_y == 4) || (tile_x == 64 && (tile_y == 4 || tile_y == 8)) ||
+               (tile_x == 32 && (tile_y == 8 || tile_y == 16));
     return tile_y == 1 && (tile_x == 64 || tile_x == 128 || tile_x == 256);
 }
 
@@ -574,10 +789,23 @@ template <class L, class S>
 void default_fused_shape(const Geom &g, int &tx, int &ty, int &chunk)
 {
     if (L::D == 3) {
-        // measured on 256^3: 64x8 is fastest for FP32, 64x4 for 16-bit storage
-        tx = 64;
-        ty = sizeof(S) == 2 ? 4 : 8;
-        chunk = 64;
+        // Measured on 256^3.  FP32: full-width rows (256x2) or 128x4 tiles
+        // walking 128 planes, one workgroup per CU: longer contiguous rows per
+        // population outweigh the larger halo.  16-bit storage: 64x4 walking
+        // 64 planes.
+        if (sizeof(S) == 4 && g.nx == 256) {
+            tx = 256;
+            ty = 2;
+            chunk = 128;
+        } else if (sizeof(S) == 4 && g.nx >= 128) {
+            tx = 128;
+            ty = 4;
+            chunk = 128;
+        } else {
+            tx = 64;
+            ty = sizeof(S) == 2 ? 4 : 8;
+            chunk = 64;
+        }
     } else {
         tx = g.nx >= 256 ? 256 : (g.nx >= 128 ? 128 : 64);
         ty = 1;
@@ -594,6 +822,7 @@ bool fused_supported(const Geom &g, int tile_x, int tile_y, int march)
     // Any lattice size otherwise: ragged tiles are masked and every plane
     // index wraps periodically (with fewer than 3 planes the ring simply holds
     // copies).
+    if (L::D == 3 && tile_x == 256 && g.nx != 256) return false;  // full-width tiles only
     return tile_x == 0 || fused_shape_valid<L, S>(tile_x, tile_y, march);
 }
 
@@ -626,6 +855,8 @@ hipError_t launch_fused(const StepArgs<L, S> &a, int tile_x, int tile_y, int mar
         }
         if (chunk == 0) chunk = dch;
         if constexpr (L::D == 3) {
+            if (tx == 256 && ty == 2) return launch_fused_shape<L, S, 256, 2>(a, chunk, stream);
+            if (tx == 128 && ty == 4) return launch_fused_shape<L, S, 128, 4>(a, chunk, stream);
             if (tx == 64 && ty == 4) return launch_fused_shape<L, S, 64, 4>(a, chunk, stream);
             if (tx == 64 && ty == 8) return launch_fused_shape<L, S, 64, 8>(a, chunk, stream);
             if (tx == 32 && ty == 8) return launch_fused_shape<L, S, 32, 8>(a, chunk, stream);

@@ -648,7 +648,10 @@ fmlb_status fmlb_set_tile(fmlb_ctx *c, int tile_x, int tile_y, int march)
         using L = decltype(l);
         using S = std::remove_pointer_t<decltype(sp)>;
         if (tile_x == 1) return FMLB_OK;  // two-pass form
-        if ((tile_x || tile_y || march) && !fused_shape_valid<L, S>(tile_x, tile_y, march)) return FMLB_E_INVALID;
+        if (march > 4096) return FMLB_E_INVALID;
+        if (tile_x == 0 && tile_y == 0) return FMLB_OK;  // default tile, given or default march
+        if (!fused_shape_valid<L, S>(tile_x, tile_y, march)) return FMLB_E_INVALID;
+        if (!fused_supported<L, S>(c->g, tile_x, tile_y, march)) return FMLB_E_INVALID;
         return FMLB_OK;
     });
     if (st) return st;

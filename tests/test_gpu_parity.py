@@ -263,7 +263,8 @@ def test_full_size_c2_sampled(fm, orc):
 
 
 @pytest.mark.parametrize("lattice,shape,tiles", [
-    ("d3q19", (20, 19, 70), [(1, 0, 0), (64, 4, 7), (64, 8, 32), (32, 8, 3), (32, 16, 5)]),
+    ("d3q19", (20, 19, 70), [(1, 0, 0), (64, 4, 7), (64, 8, 32), (32, 8, 3), (32, 16, 5), (128, 4, 9)]),
+    ("d3q19", (7, 5, 256), [(1, 0, 0), (256, 2, 3), (256, 2, 64), (128, 4, 2), (0, 0, 0)]),
     ("d2q9", (1, 37, 300), [(1, 0, 0), (64, 1, 5), (128, 1, 16), (256, 1, 2)]),
 ])
 @pytest.mark.parametrize("storage", ["f32", "bf16", "f16"])
@@ -288,6 +289,14 @@ def test_launch_shape_invariance_bitwise(fm, lattice, shape, tiles, storage):
             ref = raw
         else:
             assert np.array_equal(raw, ref), t
+
+
+def test_full_width_tiles_need_matching_width(fm):
+    g = fm.Lattice(fm.Params(lattice="d3q19", storage="f32", nx=128, ny=8, nz=8))
+    with pytest.raises(fm.FmlbError):
+        g.set_tile(256, 2, 16)
+    g.set_tile(128, 4, 16)
+    g.close()
 
 
 def test_fp64_rejects_fused_shapes(fm):
