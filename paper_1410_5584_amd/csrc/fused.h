@@ -791,8 +791,8 @@ void default_fused_shape(const Geom &g, int &tx, int &ty, int &chunk)
     if (L::D == 3) {
         // Measured on 256^3.  FP32: full-width rows (256x2) or 128x4 tiles
         // walking 128 planes, one workgroup per CU: longer contiguous rows per
-        // population outweigh the larger halo.  16-bit storage: 64x4 walking
-        // 64 planes.
+        // population outweigh the larger halo.  16-bit storage: 64x8 walking
+        // 128 planes.
         if (sizeof(S) == 4 && g.nx == 256) {
             tx = 256;
             ty = 2;
@@ -801,9 +801,13 @@ void default_fused_shape(const Geom &g, int &tx, int &ty, int &chunk)
             tx = 128;
             ty = 4;
             chunk = 128;
+        } else if (sizeof(S) == 2) {
+            tx = 64;
+            ty = 8;
+            chunk = 128;
         } else {
             tx = 64;
-            ty = sizeof(S) == 2 ? 4 : 8;
+            ty = 8;
             chunk = 64;
         }
     } else {
