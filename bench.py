@@ -133,8 +133,16 @@ def time_steps(fm, torch, storage: str, steps: int, warmup: int, work=WORKLOAD):
     ms = start.elapsed_time(end)
     sums = lat.global_sums()
     health = lat.health()
+    # roofline reference: a plain copy with the step's pull addresses
+    lat.copy_reference()
+    start.record(stream)
+    for _ in range(steps):
+        lat.copy_reference()
+    end.record(stream)
+    torch.cuda.synchronize()
+    ms_copy = start.elapsed_time(end)
     lat.close()
-    return ms, p.nx * p.ny * p.nz, sums, health
+    return ms, p.nx * p.ny * p.nz, sums, health, ms_copy
 
 
 def batched(fm, torch, steps: int, warmup: int, plain_steps: int):
@@ -237,7 +245,7 @@ def main() -> int:
     fm.lib()
     torch.cuda.set_device(0)
 
-    ms, nsites, sums, health = time_steps(fm, torch, "f32", args.steps, args.warmup)
+    ms, nsites, sums, health, ms_copy = time_steps(fm, torch, "f32", args.steps, args.warmup)
     ms_per_step = ms / args.steps
     mlups = nsites * args.steps / (ms / 1e3) / 1e6
     bps = BYTES_PER_SITE[("d3q19", "f32")]
@@ -253,20 +261,24 @@ def main() -> int:
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None if traffic is None else round(traffic),
-                     "algorithmic_bytes_per_launch": bps * nsites},
+                     "algorithmic_bytes_per_launch": bps * nsites,
+                     "copy_reference": {
+                         "ms_per_launch": round(ms_copy / args.steps, 4),
+                         "frac": round(bps * nsites / (ms_copy / args.steps / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                         "note": "plain copy with the step's pull addresses (fmlb_copy_reference)"}},
         "checks": {"mass": [float(sums[0]), float(sums[1])], "health": list(health)},
     }
     if not args.no_variants:
         var = {}
         for storage in ("bf16", "f16"):
-            ms16, _, _, h16 = time_steps(fm, torch, storage, args.steps, args.warmup)
+            ms16, _, _, h16, _ = time_steps(fm, torch, storage, args.steps, args.warmup)
             m16 = nsites * args.steps / (ms16 / 1e3) / 1e6
             var[f"d3q19_256cube_{storage}_dev"] = {
                 "value": round(m16, 2), "unit": "MLUPS", "ms_per_step": round(ms16 / args.steps, 4),
                 "vs_f32": round(m16 / mlups, 3),
                 "hbm_frac": round(BYTES_PER_SITE[("d3q19", storage)] * nsites / (ms16 / args.steps / 1e3) / 1e9
                                   / HBM_PEAK_GBS, 4)}
-        ms1, n1, _, _ = time_steps(fm, torch, "f32", args.steps, args.warmup, work=C1)
+        ms1, n1, _, _, _ = time_steps(fm, torch, "f32", args.steps, args.warmup, work=C1)
         var["d2q9_1024sq_f32"] = {"value": round(n1 * args.steps / (ms1 / 1e3) / 1e6, 2), "unit": "MLUPS",
                                   "ms_per_step": round(ms1 / args.steps, 4),
                                   "note": "75 MB per buffer, cache-resident: HBM fraction not meaningful"}

@@ -209,6 +209,16 @@ fmlb_status fmlb_health(fmlb_ctx *ctx, int64_t counts[2]);
  * bits).  FMLB_E_INVALID for an unsupported shape. */
 fmlb_status fmlb_set_tile(fmlb_ctx *ctx, int tile_x, int tile_y, int march);
 
+/* Memory reference for the roofline (not part of the method): one launch of
+ * a plain copy kernel that reads every population of the current state with
+ * the pull offsets of a step (one site per thread, workgroups in row order)
+ * and writes it unchanged to the other buffer: the same bytes and addresses
+ * as one step, with no halo, no ring, no arithmetic.  Its time is the
+ * practical floor of the step's traffic on the device.  The state is not
+ * changed (the other buffer is scratch between steps; the step counter does
+ * not advance).  Asynchronous. */
+fmlb_status fmlb_copy_reference(fmlb_ctx *ctx);
+
 /* Human-readable name of a status code; the last HIP error code of any call. */
 const char *fmlb_status_string(fmlb_status s);
 int32_t fmlb_last_hip_error(void);

@@ -77,6 +77,7 @@ _SIGNATURES = {
     "fmlb_load_raw": (ctypes.c_int32, [_vp, _vp, ctypes.c_size_t, ctypes.c_int64]),
     "fmlb_health": (ctypes.c_int32, [_vp, _i64p]),
     "fmlb_set_tile": (ctypes.c_int32, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "fmlb_copy_reference": (ctypes.c_int32, [_vp]),
     "fmlb_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
     "fmlb_last_hip_error": (ctypes.c_int32, []),
     "fmlb_batch_required_bytes": (ctypes.c_size_t, [_pp, ctypes.c_int, ctypes.c_int]),
@@ -307,6 +308,10 @@ def fmlb_batch_reset_modes(b: int):
     _check("fmlb_batch_reset_modes", lib().fmlb_batch_reset_modes(_vp(b)))
 
 
+def fmlb_copy_reference(ctx: int):
+    _check("fmlb_copy_reference", lib().fmlb_copy_reference(_vp(ctx)))
+
+
 # ---- convenience wrapper: torch-owned buffers, numpy host arrays ------------
 
 @dataclass
@@ -428,6 +433,10 @@ class Lattice:
 
     def set_tile(self, tile_x: int = 0, tile_y: int = 0, march: int = 0):
         fmlb_set_tile(self.ctx, tile_x, tile_y, march)
+
+    def copy_reference(self):
+        """One launch of the roofline reference copy (state unchanged)."""
+        fmlb_copy_reference(self.ctx)
 
     def synchronize(self):
         self.stream.synchronize()

@@ -175,4 +175,28 @@ __global__ __launch_bounds__(256) void scatter_pop_kernel(S *dst, const double *
     store_pop<L, S>(dst, g.nsites, s, i, site, (Real)in[nsite], ref);
 }
 
+// Roofline reference: the pulls and stores of one step with no arithmetic
+// (buf_i(r) of the destination = pre-collision f_bar_i(r)).
+template <class L, class S>
+__global__ __launch_bounds__(256) void pull_copy_kernel(const S *src, S *dst, Geom g)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y, z = blockIdx.z;
+    if (x >= g.nx) return;
+    const size_t site = (size_t)x + (size_t)g.nx * ((size_t)y + (size_t)g.ny * (size_t)z);
+    S v[2][L::Q];
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        const int xs = wrap(x, -L::cx[i], g.nx), ys = wrap(y, -L::cy[i], g.ny);
+        const int zs = L::D == 3 ? wrap(z, -L::cz[i], g.nz) : 0;
+        const size_t s2 = (size_t)xs + (size_t)g.nx * ((size_t)ys + (size_t)g.ny * (size_t)zs);
+#pragma unroll
+        for (int s = 0; s < 2; ++s) v[s][i] = src[((size_t)(s * L::Q + i)) * g.nsites + s2];
+    }
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i)
+#pragma unroll
+        for (int s = 0; s < 2; ++s) dst[((size_t)(s * L::Q + i)) * g.nsites + site] = v[s][i];
+}
+
 }  // namespace fmlb

@@ -675,6 +675,22 @@ const char *fmlb_status_string(fmlb_status s)
     return "unknown status";
 }
 
+fmlb_status fmlb_copy_reference(fmlb_ctx *c)
+{
+    if (!c) return FMLB_E_NULL;
+    if (!c->ready) return FMLB_E_STATE;
+    return dispatch(c, [&](auto l, auto sp) -> fmlb_status {
+        using L = decltype(l);
+        using S = std::remove_pointer_t<decltype(sp)>;
+        const SiteGrid sg = site_grid(c->g);
+        hipLaunchKernelGGL((pull_copy_kernel<L, S>), sg.grid, sg.block, 0, c->stream,
+                           reinterpret_cast<const S *>(c->pops[c->cur]), reinterpret_cast<S *>(c->pops[1 - c->cur]),
+                           c->g);
+        LAUNCH_CHECK();
+        return FMLB_OK;
+    });
+}
+
 int32_t fmlb_last_hip_error(void) { return g_last_hip; }
 
 }  // extern "C"

@@ -304,3 +304,27 @@ def test_fp64_rejects_fused_shapes(fm):
     g.set_tile(1, 0, 0)
     with pytest.raises(fm.FmlbError):
         g.set_tile(64, 4, 8)
+
+
+def test_copy_reference_leaves_state_unchanged(fm):
+    """The roofline reference copy reads the state and overwrites only the
+    other buffer: populations, step counter and the next step are unchanged."""
+    import workloads
+    shape = (6, 5, 70)
+    r1, r2 = workloads.initial_density(shape, "perturbed", seed=3, amplitude=0.05)
+    runs = []
+    for copy in (False, True):
+        g = fm.Lattice(fm.Params(lattice="d3q19", storage="f32", nx=70, ny=5, nz=6, tau=(0.8, 1.2), tau_d=1.0,
+                                 G=0.5, kT=1e-4, seed=2))
+        g.init_density(r1, r2)
+        g.step(3)
+        before = g.populations()
+        if copy:
+            for _ in range(3):
+                g.copy_reference()
+            assert np.array_equal(g.populations(), before)
+            assert g.step_count == 3
+        g.step(2)
+        runs.append(g.save_raw()[0])
+        g.close()
+    assert np.array_equal(runs[0], runs[1])
