@@ -73,8 +73,11 @@ enum {
 typedef enum { FMLB_D2Q9 = 0, FMLB_D3Q19 = 1 } fmlb_lattice;
 
 /* Storage of the populations in device memory.  The arithmetic is FP64 for
- * FMLB_F64 and FP32 for every other storage.  The 16-bit forms store the
- * deviation f_i - w_i rho_ref (rounded to nearest even). */
+ * FMLB_F64 and FP32 for every other storage.  FP32 and the 16-bit forms
+ * store the deviation f_i - w_i rho_ref (16-bit: rounded to nearest even),
+ * and the FP32 step updates the deviations directly, so its rounding is
+ * relative to the fluctuations rather than to w_i rho.  FP64 stores
+ * absolute values. */
 typedef enum {
     FMLB_F64 = 0,
     FMLB_F32 = 1,
@@ -98,7 +101,7 @@ typedef struct fmlb_params {
                            (Eq. (37): common, so total momentum is conserved); > 1/2       */
     double G;           /* coupling of the lattice force, Eq. (87) (G = G')               */
     double kT;          /* k_B T >= 0; mu = k_B T / c_s^2 with c_s^2 = 1/3 (Eq. (18))      */
-    double rho_ref[2];  /* reference density per species for the 16-bit deviation storage */
+    double rho_ref[2];  /* reference density per species for the FP32 / 16-bit deviation storage */
     uint64_t seed;      /* Philox key                                                      */
     uint32_t flags;     /* FMLB_NOISE_* bits                                               */
 } fmlb_params;
@@ -188,7 +191,9 @@ fmlb_status fmlb_get_populations(fmlb_ctx *ctx, double *host, size_t bytes);
 fmlb_status fmlb_set_populations(fmlb_ctx *ctx, const double *host, size_t bytes, int64_t step);
 
 /* Bit-exact checkpoint of the stored state in its device representation
- * (fmlb_required_bytes(p, FMLB_BUF_POPS_A) bytes) plus the step counter.
+ * (fmlb_required_bytes(p, FMLB_BUF_POPS_A) bytes: deviations from w_i rho_ref
+ * for FP32 and 16-bit storage, so restore into a lattice with the same
+ * rho_ref) plus the step counter.
  * Restoring and stepping reproduces an uninterrupted run bit for bit.
  * Synchronise. */
 fmlb_status fmlb_save_raw(fmlb_ctx *ctx, void *host, size_t bytes, int64_t *step);
@@ -204,9 +209,12 @@ fmlb_status fmlb_health(fmlb_ctx *ctx, int64_t counts[2]);
  * D2Q9, where tile_y must be 1) and `march` planes walked per workgroup.
  * Supported tiles: D3Q19 256x2 (full-width rows: only for nx = 256), 128x4,
  * 64x4, 64x8, 32x8, 32x16; D2Q9 64x1, 128x1, 256x1; march 1..4096.
- * 0 = default for each argument.  tile_x = 1 selects the two-pass form (a
- * density pass, then the step).  Results do not depend on the choice (same
- * bits).  FMLB_E_INVALID for an unsupported shape. */
+ * 0 = default for each argument: the tile from the lattice width and the
+ * storage, the march the longest that still gives about one workgroup per
+ * CU (D3Q19) or per two tile rows (small D2Q9 lattices, which are bound by
+ * latency).  tile_x = 1 selects the two-pass form (a density pass, then the
+ * step).  Results do not depend on the choice (same bits).  FMLB_E_INVALID
+ * for an unsupported shape. */
 fmlb_status fmlb_set_tile(fmlb_ctx *ctx, int tile_x, int tile_y, int march);
 
 /* Memory reference for the roofline (not part of the method): one launch of

@@ -346,7 +346,7 @@ __device__ __forceinline__ Real relax_add(int i, Real base, Real x)
 // Collision of species s at one site, in place.  zmom: the D momentum
 // normals; zmode: the NS normals of this species' non-hydrodynamic modes.
 template <class L, class Real>
-__device__ __forceinline__ void collide_species(int s, Real (&f)[L::Q], Real r, const Real (&js)[3],
+__device__ __forceinline__ void collide_species(int s, Real (&f)[L::Q], Real r, Real dr, const Real (&js)[3],
                                                 const Real (&a)[3], const SiteCommon<Real> &c,
                                                 const Phys<Real> &ph, const Real *zmom, const Real *zmode)
 {
@@ -385,7 +385,7 @@ __device__ __forceinline__ void collide_species(int s, Real (&f)[L::Q], Real r, 
     const Real Mxy2 = Real(9) * Pc(0, 1) + Real(2) * mn.Nxy;  // 2 M_xy
     const Real Myz2 = D == 3 ? Real(9) * Pc(1, 2) + Real(2) * mn.Nyz : Real(0);
     const Real Mxz2 = D == 3 ? Real(9) * Pc(0, 2) + Real(2) * mn.Nxz : Real(0);
-    const Real A = lr - (Mxx + Myy + Mzz) * Real(1.0 / 3.0);
+    const Real A = lam * dr - (Mxx + Myy + Mzz) * Real(1.0 / 3.0);
     const Real Vx = Real(3) * (lam * js[0] + R[0]);
     const Real Vy = Real(3) * (lam * js[1] + R[1]);
     const Real Vz = D == 3 ? Real(3) * (lam * js[2] + R[2]) : Real(0);
@@ -419,16 +419,25 @@ __device__ __forceinline__ void collide_species(int s, Real (&f)[L::Q], Real r, 
 }
 
 // Collide both species at one site in place, species 1 first.  f holds the
-// pre-collision populations pulled to the site, rho / j their moments
-// (moments()), acc the accelerations of Eq. (87).  store(s, f[s]) is called
+// pre-collision populations pulled to the site as deviations d_i = f_i -
+// w_i ref_sigma from a reference density (ref = 0: absolute values), drho /
+// j their moments (moments(): drho = rho - ref, j unchanged because
+// sum_i w_i c_i = 0), acc the accelerations of Eq. (87) (which likewise only
+// see density differences).  The update is written for the deviations:
+// since (1 - lambda) + lambda = 1, f*_i - w_i ref = (1 - lambda) d_i +
+// w_i [lambda drho - tr(M)/3 + ...], so every term is of the size of the
+// deviations and FP32 rounding stays at their scale (with absolute FP32
+// values the rounding of terms of size w_i rho is not symmetric for smooth
+// fields and drifts the mass by ~1e-8 per step).  store(s, f[s]) is called
 // as soon as species s is done, so its registers can be released early.
 template <class L, class Real, class StoreFn>
-__device__ __forceinline__ void collide_site(Real (&f)[2][L::Q], const Real (&rho)[2], const Real (&j)[2][3],
-                                             const Real (&acc)[2][3], const Phys<Real> &ph, const Counter &ctr,
-                                             StoreFn &&store)
+__device__ __forceinline__ void collide_site(Real (&f)[2][L::Q], const Real (&drho)[2], const Real (&j)[2][3],
+                                             const Real (&acc)[2][3], const Phys<Real> &ph, const Real (&ref)[2],
+                                             const Counter &ctr, StoreFn &&store)
 {
     constexpr int D = L::D;
     using SN = SiteNormals<L, Real>;
+    const Real rho[2] = {ref[0] + drho[0], ref[1] + drho[1]};
     const SiteCommon<Real> c = site_common<L, Real>(rho, j, acc, ph);
     SN sn;
     Real zmom[3] = {0, 0, 0};
@@ -437,13 +446,13 @@ __device__ __forceinline__ void collide_site(Real (&f)[2][L::Q], const Real (&rh
         sn.stage1(ph, ctr, z1);
 #pragma unroll
         for (int al = 0; al < D; ++al) zmom[al] = z1[al];
-        collide_species<L, Real>(0, f[0], rho[0], j[0], acc[0], c, ph, zmom, z1 + D);
+        collide_species<L, Real>(0, f[0], rho[0], drho[0], j[0], acc[0], c, ph, zmom, z1 + D);
     }
     store(0, f[0]);
     {
         Real z2[SN::K2];
         sn.stage2(ph, ctr, z2);
-        collide_species<L, Real>(1, f[1], rho[1], j[1], acc[1], c, ph, zmom, z2);
+        collide_species<L, Real>(1, f[1], rho[1], drho[1], j[1], acc[1], c, ph, zmom, z2);
     }
     store(1, f[1]);
 }

@@ -170,7 +170,8 @@ __device__ __forceinline__ void fused_tile(const StepArgs<L, S> &a, int t0, int 
         hp1 = D3 ? ((t1 * T1 - OFF1 + h1) % n1 + n1) % n1 : 0;
     }
 
-    const Real ref[2] = {a.ref[0], a.ref[1]};
+    // reference density of the stored deviations (0 for absolute storage)
+    const Real ref[2] = {Storage<S>::deviation ? a.ref[0] : Real(0), Storage<S>::deviation ? a.ref[1] : Real(0)};
     auto slot = [&](int m) { return (m - mbeg + 1) & 3; };
 
     // Pull the 2Q populations of plane-site (q0, q1) on plane m (m wrapped).
@@ -184,7 +185,6 @@ __device__ __forceinline__ void fused_tile(const StepArgs<L, S> &a, int t0, int 
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
                 Real v = BufIO<S>::load(rsrc[s], voff, (uint32_t)i * pop_bytes);
-                if (Storage<S>::deviation) v += Real(L::w36[i]) / Real(36) * ref[s];
                 f[s][i] = v;
             }
         }
@@ -253,12 +253,11 @@ __device__ __forceinline__ void fused_tile(const StepArgs<L, S> &a, int t0, int 
             lattice_acceleration<L, Real>(nb, a.ph.negG, acc);
             const uint32_t site = (uint32_t)p0 + s1 * (uint32_t)(D3 ? p1 : 0) + sm * (uint32_t)m;
             const uint32_t voff = site * ES;
-            collide_site<L, Real>(cur, rc, jc, acc, a.ph, Counter{site, a.step_lo, a.step_hi},
+            collide_site<L, Real>(cur, rc, jc, acc, a.ph, ref, Counter{site, a.step_lo, a.step_hi},
                                   [&](int s, auto &fs) {
 #pragma unroll
                                       for (int i = 0; i < Q; ++i) {
                                           Real v = fs[i];
-                                          if (Storage<S>::deviation) v -= Real(L::w36[i]) / Real(36) * ref[s];
                                           BufIO<S>::store(v, rdst[s], voff, (uint32_t)i * pop_bytes);
                                       }
                                   });
@@ -388,7 +387,8 @@ __device__ __forceinline__ void fused_tile_async(const StepArgs<L, S> &a, int t0
         hp1 = D3 ? ((t1 * T1 - OFF1 + h1) % n1 + n1) % n1 : 0;
     }
 
-    const Real ref[2] = {a.ref[0], a.ref[1]};
+    // reference density of the stored deviations (0 for absolute storage)
+    const Real ref[2] = {Storage<S>::deviation ? a.ref[0] : Real(0), Storage<S>::deviation ? a.ref[1] : Real(0)};
     auto slot = [&](int m) { return (m - mbeg + 1) & 3; };
     auto wrapm = [&](int m) { return m < 0 ? m + nm : (m >= nm ? m - nm : m); };
     auto pull_off = [&](int q0, int q1, int m, int i) -> uint32_t {
@@ -405,7 +405,6 @@ __device__ __forceinline__ void fused_tile_async(const StepArgs<L, S> &a, int t0
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
                 Real v = BufIO<S>::load(rsrc[s], voff, (uint32_t)i * pop_bytes);
-                if (Storage<S>::deviation) v += Real(L::w36[i]) / Real(36) * ref[s];
                 f[s][i] = v;
             }
         }
@@ -431,7 +430,6 @@ __device__ __forceinline__ void fused_tile_async(const StepArgs<L, S> &a, int t0
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
                 Real v = DmaWord<S>::decode(rows[(s * Q + i) * len + idx]);
-                if (Storage<S>::deviation) v += Real(L::w36[i]) / Real(36) * ref[s];
                 f[s][i] = v;
             }
     };
@@ -512,12 +510,11 @@ __device__ __forceinline__ void fused_tile_async(const StepArgs<L, S> &a, int t0
         __builtin_amdgcn_sched_barrier(0);
         const uint32_t site = (uint32_t)p0 + s1 * (uint32_t)(D3 ? p1 : 0) + sm * (uint32_t)m;
         const uint32_t voff = site * ES;
-        collide_site<L, Real>(cur, rc, jc, acc, a.ph, Counter{site, a.step_lo, a.step_hi}, [&](int s, auto &fs) {
+        collide_site<L, Real>(cur, rc, jc, acc, a.ph, ref, Counter{site, a.step_lo, a.step_hi}, [&](int s, auto &fs) {
             if (inside) {
 #pragma unroll
                 for (int i = 0; i < Q; ++i) {
                     Real v = fs[i];
-                    if (Storage<S>::deviation) v -= Real(L::w36[i]) / Real(36) * ref[s];
                     BufIO<S>::store(v, rdst[s], voff, (uint32_t)i * pop_bytes);
                 }
             }
@@ -605,7 +602,8 @@ __device__ __forceinline__ void fused_tile_rows(const StepArgs<L, S> &a, int t0,
         if (lx == T0 - 1) row_plane[box - T0] = v;
     };
 
-    const Real ref[2] = {a.ref[0], a.ref[1]};
+    // reference density of the stored deviations (0 for absolute storage)
+    const Real ref[2] = {Storage<S>::deviation ? a.ref[0] : Real(0), Storage<S>::deviation ? a.ref[1] : Real(0)};
     auto slot = [&](int m) { return (m - mbeg + 1) & 3; };
     auto wrapm = [&](int m) { return m < 0 ? m + nm : (m >= nm ? m - nm : m); };
     auto pull_off = [&](int q0, int q1, int m, int i) -> uint32_t {
@@ -622,7 +620,6 @@ __device__ __forceinline__ void fused_tile_rows(const StepArgs<L, S> &a, int t0,
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
                 Real v = BufIO<S>::load(rsrc[s], voff, (uint32_t)i * pop_bytes);
-                if (Storage<S>::deviation) v += Real(L::w36[i]) / Real(36) * ref[s];
                 f[s][i] = v;
             }
         }
@@ -648,7 +645,6 @@ __device__ __forceinline__ void fused_tile_rows(const StepArgs<L, S> &a, int t0,
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
                 Real v = DmaWord<S>::decode(rows[(s * Q + i) * len + idx]);
-                if (Storage<S>::deviation) v += Real(L::w36[i]) / Real(36) * ref[s];
                 f[s][i] = v;
             }
     };
@@ -729,12 +725,11 @@ __device__ __forceinline__ void fused_tile_rows(const StepArgs<L, S> &a, int t0,
         __builtin_amdgcn_sched_barrier(0);
         const uint32_t site = (uint32_t)p0 + s1 * (uint32_t)(D3 ? p1 : 0) + sm * (uint32_t)m;
         const uint32_t voff = site * ES;
-        collide_site<L, Real>(cur, rc, jc, acc, a.ph, Counter{site, a.step_lo, a.step_hi}, [&](int s, auto &fs) {
+        collide_site<L, Real>(cur, rc, jc, acc, a.ph, ref, Counter{site, a.step_lo, a.step_hi}, [&](int s, auto &fs) {
             if (inside) {
 #pragma unroll
                 for (int i = 0; i < Q; ++i) {
                     Real v = fs[i];
-                    if (Storage<S>::deviation) v -= Real(L::w36[i]) / Real(36) * ref[s];
                     BufIO<S>::store(v, rdst[s], voff, (uint32_t)i * pop_bytes);
                 }
             }
@@ -789,31 +784,39 @@ template <class L, class S>
 void default_fused_shape(const Geom &g, int &tx, int &ty, int &chunk)
 {
     if (L::D == 3) {
-        // Measured on 256^3.  FP32: full-width rows (256x2) or 128x4 tiles
-        // walking 128 planes, one workgroup per CU: longer contiguous rows per
-        // population outweigh the larger halo.  16-bit storage: 64x8 walking
-        // 128 planes.
+        // Tiles measured on 256^3 (FP32: full-width 256x2 rows, else 128x4;
+        // 16-bit: 64x8) and from 16^3 to 128^3 (narrower tiles for narrower
+        // lattices).  The march is then the longest that still gives one
+        // workgroup per CU (256): fewer workgroups leave CUs idle, while more,
+        // shorter marches re-read more halo planes (128^3 FP32: 149 us at 256
+        // workgroups, 160 us at 512, 252 us at 128).
         if (sizeof(S) == 4 && g.nx == 256) {
             tx = 256;
             ty = 2;
-            chunk = 128;
         } else if (sizeof(S) == 4 && g.nx >= 128) {
             tx = 128;
             ty = 4;
-            chunk = 128;
-        } else if (sizeof(S) == 2) {
+        } else if (g.nx >= 64) {
             tx = 64;
-            ty = 8;
-            chunk = 128;
+            ty = sizeof(S) == 4 ? 4 : 8;
         } else {
-            tx = 64;
+            tx = 32;
             ty = 8;
-            chunk = 64;
         }
+        const long cols = (long)((g.nx + tx - 1) / tx) * (long)((g.ny + ty - 1) / ty);
+        chunk = 2;
+        while (chunk < 128 && cols * ((g.nz + 2L * chunk - 1) / (2L * chunk)) >= 256) chunk *= 2;
     } else {
+        // Measured from 64x2 to 1024^2 (FP32): a small lattice is bound by
+        // the latency of one row, so it wants as many workgroups as it has
+        // tile rows; from about 2000 tile rows on, marching several rows per
+        // workgroup (re-using the force ring) wins, up to 8 rows at 1024^2.
         tx = g.nx >= 256 ? 256 : (g.nx >= 128 ? 128 : 64);
         ty = 1;
-        chunk = 16;
+        const long rows = (long)((g.nx + tx - 1) / tx) * (long)g.ny;
+        chunk = 1;
+        while (chunk < 16 && rows / (2L * chunk) >= 512) chunk *= 2;
+        if (chunk < 4) chunk = 1;
     }
 }
 

@@ -38,13 +38,24 @@ __device__ __forceinline__ typename Storage<S>::Real load_pop(const S *buf, size
     return v;
 }
 
+// FP64 value v written to population (s, i) of a site: the deviation from
+// w_i ref is formed in FP64, then rounded once to the storage format (host
+// I/O and initial states).
 template <class L, class S>
-__device__ __forceinline__ void store_pop(S *buf, size_t nsites, int s, int i, size_t site,
-                                          typename Storage<S>::Real v, typename Storage<S>::Real ref)
+__device__ __forceinline__ void store_pop_f64(S *buf, size_t nsites, int s, int i, size_t site, double v, double ref)
 {
     using Real = typename Storage<S>::Real;
-    if (Storage<S>::deviation) v -= Real(L::w36[i]) / Real(36) * ref;
-    Storage<S>::store(buf, ((size_t)(s * L::Q + i)) * nsites + site, v);
+    if (Storage<S>::deviation) v -= (double)L::w36[i] / 36.0 * ref;
+    Storage<S>::store(buf, ((size_t)(s * L::Q + i)) * nsites + site, (Real)v);
+}
+
+// Absolute FP64 value of a stored population.
+template <class L, class S>
+__device__ __forceinline__ double load_pop_f64(const S *buf, size_t nsites, int s, int i, size_t site, double ref)
+{
+    double v = (double)Storage<S>::load(buf, ((size_t)(s * L::Q + i)) * nsites + site);
+    if (Storage<S>::deviation) v += (double)L::w36[i] / 36.0 * ref;
+    return v;
 }
 
 // Pull the 2Q pre-collision populations of site (x, y, z).
@@ -64,6 +75,23 @@ __device__ __forceinline__ void pull_site(const S *src, const Geom &g, int x, in
     }
 }
 
+// Pull the 2Q stored values of site (x, y, z) as they are (deviations from
+// w_i rho_ref for deviation storage), for the step kernels.
+template <class L, class S>
+__device__ __forceinline__ void pull_site_stored(const S *src, const Geom &g, int x, int y, int z,
+                                                 typename Storage<S>::Real (&f)[2][L::Q])
+{
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        const int xs = wrap(x, -L::cx[i], g.nx);
+        const int ys = wrap(y, -L::cy[i], g.ny);
+        const int zs = L::D == 3 ? wrap(z, -L::cz[i], g.nz) : 0;
+        const size_t site = (size_t)xs + (size_t)g.nx * ((size_t)ys + (size_t)g.ny * (size_t)zs);
+#pragma unroll
+        for (int s = 0; s < 2; ++s) f[s][i] = Storage<S>::load(src, ((size_t)(s * L::Q + i)) * g.nsites + site);
+    }
+}
+
 template <class L, class S>
 __global__ __launch_bounds__(256) void density_kernel(StepArgs<L, S> a)
 {
@@ -72,13 +100,13 @@ __global__ __launch_bounds__(256) void density_kernel(StepArgs<L, S> a)
     const int y = blockIdx.y, z = blockIdx.z;
     if (x >= a.g.nx) return;
     Real f[2][L::Q];
-    pull_site<L, S>(a.src, a.g, x, y, z, a.ref, f);
+    pull_site_stored<L, S>(a.src, a.g, x, y, z, f);
     const size_t site = (size_t)x + (size_t)a.g.nx * ((size_t)y + (size_t)a.g.ny * (size_t)z);
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
         Real r, j[3];
         moments<L, Real>(f[s], r, j);
-        a.rho[(size_t)s * a.g.nsites + site] = r;
+        a.rho[(size_t)s * a.g.nsites + site] = r;  // rho - rho_ref for deviation storage
     }
 }
 
@@ -91,7 +119,7 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs<L, S> a)
     if (x >= a.g.nx) return;
     const Geom g = a.g;
     Real f[2][L::Q];
-    pull_site<L, S>(a.src, g, x, y, z, a.ref, f);
+    pull_site_stored<L, S>(a.src, g, x, y, z, f);
     const Real *rho = a.rho;
     auto nb = [&](int i, int s) -> Real {
         const int xn = wrap(x, L::cx[i], g.nx);
@@ -105,11 +133,13 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs<L, S> a)
     Real rho_s[2], j_s[2][3];
 #pragma unroll
     for (int s = 0; s < 2; ++s) moments<L, Real>(f[s], rho_s[s], j_s[s]);
-    collide_site<L, Real>(f, rho_s, j_s, acc, a.ph, Counter{(uint32_t)site, a.step_lo, a.step_hi},
+    // reference density of the stored deviations (0 for absolute storage)
+    const Real ref[2] = {Storage<S>::deviation ? a.ref[0] : Real(0), Storage<S>::deviation ? a.ref[1] : Real(0)};
+    collide_site<L, Real>(f, rho_s, j_s, acc, a.ph, ref, Counter{(uint32_t)site, a.step_lo, a.step_hi},
                           [&](int s, auto &fs) {
 #pragma unroll
                               for (int i = 0; i < L::Q; ++i)
-                                  store_pop<L, S>(a.dst, g.nsites, s, i, site, fs[i], a.ref[s]);
+                                  Storage<S>::store(a.dst, ((size_t)(s * L::Q + i)) * g.nsites + site, fs[i]);
                           });
 }
 
@@ -120,7 +150,6 @@ __global__ __launch_bounds__(256) void init_kernel(S *dst, const double *rho, Ge
                                                    typename Storage<S>::Real ref0,
                                                    typename Storage<S>::Real ref1)
 {
-    using Real = typename Storage<S>::Real;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y, z = blockIdx.z;
     if (x >= g.nx) return;
@@ -134,8 +163,8 @@ __global__ __launch_bounds__(256) void init_kernel(S *dst, const double *rho, Ge
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
             const double w = (double)L::w36[i] / 36.0;
-            store_pop<L, S>(dst, g.nsites, s, i, site, (Real)(w * rho[(size_t)s * g.nsites + nsite]),
-                            s == 0 ? ref0 : ref1);
+            store_pop_f64<L, S>(dst, g.nsites, s, i, site, w * rho[(size_t)s * g.nsites + nsite],
+                                (double)(s == 0 ? ref0 : ref1));
         }
     }
 }
@@ -152,11 +181,7 @@ __global__ __launch_bounds__(256) void gather_pop_kernel(const S *src, double *o
     const int xs = wrap(x, -cx, g.nx), ys = wrap(y, -cy, g.ny), zs = L::D == 3 ? wrap(z, -cz, g.nz) : 0;
     const size_t src_site = (size_t)xs + (size_t)g.nx * ((size_t)ys + (size_t)g.ny * (size_t)zs);
     const size_t site = (size_t)x + (size_t)g.nx * ((size_t)y + (size_t)g.ny * (size_t)z);
-    using Real = typename Storage<S>::Real;
-    Real v = Storage<S>::load(src, ((size_t)(s * L::Q + i)) * g.nsites + src_site);
-    double d = (double)v;
-    if (Storage<S>::deviation) d = (double)(v + Real(L::w36[i]) / Real(36) * ref);
-    out[site] = d;
+    out[site] = load_pop_f64<L, S>(src, g.nsites, s, i, src_site, (double)ref);
 }
 
 // Inverse of gather_pop_kernel: buf_i(r) = in[r + c_i].
@@ -164,7 +189,6 @@ template <class L, class S>
 __global__ __launch_bounds__(256) void scatter_pop_kernel(S *dst, const double *in, Geom g, int s, int i,
                                                           typename Storage<S>::Real ref)
 {
-    using Real = typename Storage<S>::Real;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y, z = blockIdx.z;
     if (x >= g.nx) return;
@@ -172,7 +196,7 @@ __global__ __launch_bounds__(256) void scatter_pop_kernel(S *dst, const double *
     const int xn = wrap(x, cx, g.nx), yn = wrap(y, cy, g.ny), zn = L::D == 3 ? wrap(z, cz, g.nz) : 0;
     const size_t nsite = (size_t)xn + (size_t)g.nx * ((size_t)yn + (size_t)g.ny * (size_t)zn);
     const size_t site = (size_t)x + (size_t)g.nx * ((size_t)y + (size_t)g.ny * (size_t)z);
-    store_pop<L, S>(dst, g.nsites, s, i, site, (Real)in[nsite], ref);
+    store_pop_f64<L, S>(dst, g.nsites, s, i, site, in[nsite], (double)ref);
 }
 
 // Roofline reference: the pulls and stores of one step with no arithmetic

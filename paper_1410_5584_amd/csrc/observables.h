@@ -14,13 +14,15 @@ template <class L, class S>
 __device__ __forceinline__ void pull_site_f64(const S *src, const Geom &g, int x, int y, int z,
                                               const typename Storage<S>::Real (&ref)[2], double (&f)[2][L::Q])
 {
-    using Real = typename Storage<S>::Real;
-    Real fr[2][L::Q];
-    pull_site<L, S>(src, g, x, y, z, ref, fr);
 #pragma unroll
-    for (int s = 0; s < 2; ++s)
+    for (int i = 0; i < L::Q; ++i) {
+        const int xs = wrap(x, -L::cx[i], g.nx);
+        const int ys = wrap(y, -L::cy[i], g.ny);
+        const int zs = L::D == 3 ? wrap(z, -L::cz[i], g.nz) : 0;
+        const size_t site = (size_t)xs + (size_t)g.nx * ((size_t)ys + (size_t)g.ny * (size_t)zs);
 #pragma unroll
-        for (int i = 0; i < L::Q; ++i) f[s][i] = (double)fr[s][i];
+        for (int s = 0; s < 2; ++s) f[s][i] = load_pop_f64<L, S>(src, g.nsites, s, i, site, (double)ref[s]);
+    }
 }
 
 // Site coordinates of linear index t (grid-stride helpers).

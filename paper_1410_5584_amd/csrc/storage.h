@@ -6,8 +6,11 @@
 // done by the reader).  Arrays are structure-of-arrays, [2][Q][sites], sites
 // x-fastest, so every warp-wide access to one population is contiguous.
 //
-// 16-bit formats store the deviation f_i - w_i rho_ref_sigma, rounded to
-// nearest even, and widen to FP32 on load.
+// FP32 and the 16-bit formats store the deviation d_i = f_i - w_i
+// rho_ref_sigma (16-bit: rounded to nearest even, widened to FP32 on load);
+// the step kernels update the deviations directly (collide.h), so FP32
+// rounding acts at the scale of the fluctuations, not of w_i rho.  FP64
+// stores absolute values.
 #pragma once
 
 #include <hip/hip_bf16.h>
@@ -31,7 +34,7 @@ struct Storage<double> {
 template <>
 struct Storage<float> {
     using Real = float;
-    static constexpr bool deviation = false;
+    static constexpr bool deviation = true;
     __device__ static float load(const float *p, size_t k) { return p[k]; }
     __device__ static void store(float *p, size_t k, float v) { p[k] = v; }
 };

@@ -124,7 +124,10 @@ def test_parity_16bit_deviation(fm, orc, storage, tol, lattice, shape):
 
 
 def test_conservation_on_gpu(fm):
-    for storage, tol in (("f64", 1e-13), ("f32", 2e-6)):
+    """Masses and momentum over 200 steps at tau != 1.  FP64: roundoff.
+    FP32 stores deviations from w_i rho_ref and updates them directly, so the
+    rounding is that of the 1 % perturbations: measured 6e-10 relative."""
+    for storage, tol in (("f64", 1e-13), ("f32", 2e-8)):
         _say("case conservation", storage)
         p = fm.Params(lattice="d3q19", storage=storage, nx=24, ny=20, nz=16, tau=(0.8, 1.2), tau_d=0.9,
                       G=0.8, kT=1e-4, seed=2)
