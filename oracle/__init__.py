@@ -1,10 +1,12 @@
-"""FP64 CPU oracle of the two-species fluctuating lattice Boltzmann equation.
+"""FP64 CPU oracle of the fluctuating lattice Boltzmann equation: the
+two-species model (``Sim``) and its N-species form (``MultiSim``, Apps. C
+and D).
 
 TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU-baseline
 leg of the benchmark may import this package; the product path (the HIP
 library and its binding) never does.  It shares no code with the GPU path.
 
-The stepper itself is plain C (``flbe_oracle.c``), called through ctypes.  The
+The steppers are plain C (``flbe_oracle.c``, ``flbe_multi.c``), called through ctypes.  The
 observables that are plain definitions (the structure factor of Sec. VI A and
 the mode moments of Eq. (80)) are written here with numpy.
 """
@@ -18,7 +20,8 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "flbe_oracle.c")
+_SRCS = [os.path.join(_HERE, n) for n in ("flbe_oracle.c", "flbe_multi.c")]
+_HDR = os.path.join(_HERE, "flbe_oracle.h")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 D2Q9, D3Q19 = 0, 1
@@ -27,10 +30,11 @@ NOISE_OFF, NOISE_NO_SDF = 1, 2
 
 def build(force: bool = False) -> str:
     """Compile the C oracle with gcc (-O2, OpenMP) into ``liboracle.so``."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    newest = max(os.path.getmtime(f) for f in _SRCS + [_HDR])
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < newest:
         tmp = _LIB + ".tmp"
         cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall",
-               "-o", tmp, _SRC, "-lm"]
+               "-o", tmp, *_SRCS, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
     return _LIB
@@ -41,6 +45,16 @@ class _Params(ctypes.Structure):
                 ("nz", ctypes.c_int32), ("tau", ctypes.c_double * 2), ("tau_d", ctypes.c_double),
                 ("G", ctypes.c_double), ("kT", ctypes.c_double), ("seed", ctypes.c_uint64),
                 ("flags", ctypes.c_uint32)]
+
+
+MAX_SPECIES = 4
+
+
+class _MultiParams(ctypes.Structure):
+    _fields_ = [("lattice", ctypes.c_int32), ("nspecies", ctypes.c_int32), ("nx", ctypes.c_int32),
+                ("ny", ctypes.c_int32), ("nz", ctypes.c_int32), ("tau", ctypes.c_double * MAX_SPECIES),
+                ("tau_d", ctypes.c_double), ("G", (ctypes.c_double * MAX_SPECIES) * MAX_SPECIES),
+                ("kT", ctypes.c_double), ("seed", ctypes.c_uint64), ("flags", ctypes.c_uint32)]
 
 
 _lib = None
@@ -74,6 +88,16 @@ def lib():
         L.orc_health.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]
         L.orc_num_threads.restype = ctypes.c_int
         L.orc_num_threads.argtypes = []
+        L.orc_multi_create.restype = ctypes.c_void_p
+        L.orc_multi_create.argtypes = [ctypes.POINTER(_MultiParams)]
+        L.orc_multi_destroy.argtypes = [ctypes.c_void_p]
+        L.orc_multi_current_step.restype = ctypes.c_int64
+        L.orc_multi_current_step.argtypes = [ctypes.c_void_p]
+        L.orc_multi_init_density.argtypes = [ctypes.c_void_p, dp]
+        L.orc_multi_set_populations.argtypes = [ctypes.c_void_p, dp, ctypes.c_int64]
+        L.orc_multi_get_populations.argtypes = [ctypes.c_void_p, dp]
+        L.orc_multi_step.argtypes = [ctypes.c_void_p, ctypes.c_int64]
+        L.orc_multi_moments.argtypes = [ctypes.c_void_p, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -210,6 +234,90 @@ class Sim:
         f = self.populations().reshape(2, self.Q, -1)
         m = np.einsum("ai,sin->san", self.T, f)
         return m.reshape(2, self.Q, *self.shape)
+
+
+@dataclass
+class MultiParams:
+    """N species (2..4); G is the symmetric matrix of pair couplings (Eq. (87)
+    with one coupling per pair)."""
+    lattice: int = D2Q9
+    nspecies: int = 3
+    nx: int = 16
+    ny: int = 16
+    nz: int = 1
+    tau: tuple = (1.0, 1.0, 1.0)
+    tau_d: float = 1.0
+    G: tuple = ((0.0, 0.0, 0.0), (0.0, 0.0, 0.0), (0.0, 0.0, 0.0))
+    kT: float = 0.0
+    seed: int = 1
+    flags: int = 0
+
+
+class MultiSim:
+    """The N-species oracle stepper; populations shaped [N, Q, nz, ny, nx]."""
+
+    def __init__(self, p: MultiParams):
+        L = lib()
+        n = p.nspecies
+        tau = list(p.tau) + [1.0] * (MAX_SPECIES - len(p.tau))
+        G = np.zeros((MAX_SPECIES, MAX_SPECIES))
+        G[:n, :n] = np.asarray(p.G, dtype=np.float64)
+        Gc = ((ctypes.c_double * MAX_SPECIES) * MAX_SPECIES)()
+        for a in range(MAX_SPECIES):
+            for b in range(MAX_SPECIES):
+                Gc[a][b] = G[a, b]
+        cp = _MultiParams(p.lattice, n, p.nx, p.ny, p.nz, (ctypes.c_double * MAX_SPECIES)(*tau), p.tau_d, Gc,
+                          p.kT, p.seed, p.flags)
+        h = L.orc_multi_create(ctypes.byref(cp))
+        if not h:
+            raise ValueError(f"oracle rejected parameters {p}")
+        self._h = h
+        self.p = p
+        self.N = n
+        self.c, self.w, self.T, self.Nn, self.D = basis(p.lattice)
+        self.Q = len(self.w)
+        self.shape = (p.nz, p.ny, p.nx)
+        self.nsites = p.nx * p.ny * p.nz
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib().orc_multi_destroy(h)
+            self._h = None
+
+    @property
+    def step_count(self) -> int:
+        return lib().orc_multi_current_step(self._h)
+
+    def init_density(self, rho):
+        """rho: N arrays (or scalars) of the lattice shape."""
+        r = np.stack([np.broadcast_to(np.asarray(x, dtype=np.float64), self.shape) for x in rho])
+        r = np.ascontiguousarray(r)
+        assert r.shape[0] == self.N
+        lib().orc_multi_init_density(self._h, _dp(r))
+
+    def set_populations(self, f, step: int = 0):
+        f = np.ascontiguousarray(f, dtype=np.float64).reshape(-1)
+        assert f.size == self.N * self.Q * self.nsites
+        lib().orc_multi_set_populations(self._h, _dp(f), step)
+
+    def populations(self) -> np.ndarray:
+        f = np.zeros(self.N * self.Q * self.nsites)
+        lib().orc_multi_get_populations(self._h, _dp(f))
+        return f.reshape(self.N, self.Q, *self.shape)
+
+    def step(self, n: int = 1):
+        if lib().orc_multi_step(self._h, n) != 0:
+            raise RuntimeError("orc_multi_step failed")
+
+    def moments(self):
+        """rho [N, *shape], j_bar [N, D, *shape], F [N, D, *shape]."""
+        rho = np.zeros(self.N * self.nsites)
+        j = np.zeros(self.N * self.D * self.nsites)
+        F = np.zeros(self.N * self.D * self.nsites)
+        lib().orc_multi_moments(self._h, _dp(rho), _dp(j), _dp(F))
+        return (rho.reshape(self.N, *self.shape), j.reshape(self.N, self.D, *self.shape),
+                F.reshape(self.N, self.D, *self.shape))
 
 
 def structure_factor(X: np.ndarray, Y: np.ndarray | None = None) -> np.ndarray:

@@ -85,6 +85,36 @@ int orc_health(const orc_sim *s, int64_t counts[2]);
 /* Threads the OpenMP loops use. */
 int orc_num_threads(void);
 
+/* ------------------------------------------------------------------------- */
+/* N species (flbe_multi.c): the multicomponent model of Apps. C and D.       */
+/* ------------------------------------------------------------------------- */
+#define ORC_MAX_SPECIES 4
+
+typedef struct orc_multi_params {
+    int32_t lattice;   /* ORC_D2Q9 or ORC_D3Q19 */
+    int32_t nspecies;  /* 2 .. ORC_MAX_SPECIES */
+    int32_t nx, ny, nz;
+    double tau[ORC_MAX_SPECIES];  /* transport and ghost modes of each species */
+    double tau_d;                 /* momentum modes of every species */
+    double G[ORC_MAX_SPECIES][ORC_MAX_SPECIES]; /* pair couplings, symmetric */
+    double kT;
+    uint64_t seed;
+    uint32_t flags;
+} orc_multi_params;
+
+typedef struct orc_multi orc_multi;
+
+orc_multi *orc_multi_create(const orc_multi_params *p);
+void orc_multi_destroy(orc_multi *s);
+int64_t orc_multi_current_step(const orc_multi *s);
+/* f_bar[N][Q][sites] = w_i rho[sigma][site]; step counter reset to 0. */
+int orc_multi_init_density(orc_multi *s, const double *rho);
+int orc_multi_set_populations(orc_multi *s, const double *f, int64_t step);
+int orc_multi_get_populations(const orc_multi *s, double *f);
+int orc_multi_step(orc_multi *s, int64_t n);
+/* rho[N][sites], j_bar[N][D][sites], F[N][D][sites] of the stored state (any may be NULL). */
+int orc_multi_moments(orc_multi *s, double *rho, double *j, double *F);
+
 #ifdef __cplusplus
 }
 #endif
