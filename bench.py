@@ -196,6 +196,34 @@ def batched(fm, torch, steps: int, warmup: int, plain_steps: int):
             "note": "sites fit in the 256 MB last-level cache: HBM fraction is nominal"}
 
 
+def multi_species(fm, torch, steps: int, warmup: int, n: int = 3):
+    """The N-species path (Apps. C and D) on D3Q19 256^3, FP32 deviation
+    storage, three species with pair couplings 0.5 / 0.3 / 0.4."""
+    import workloads
+    G = ((0.0, 0.5, 0.3), (0.5, 0.0, 0.4), (0.3, 0.4, 0.0))
+    p = fm.MultiParams(lattice="d3q19", storage="f32", nspecies=n, nx=256, ny=256, nz=256, tau=(1.0,) * n,
+                       tau_d=1.0, G=G, kT=1e-5, rho_ref=(1.0,) * n, seed=1)
+    m = fm.Multi(p)
+    shape = (p.nz, p.ny, p.nx)
+    m.init_density([workloads.initial_density(shape, "perturbed", seed=1 + s, amplitude=0.01)[0] for s in range(n)])
+    m.step(warmup)
+    start, end = _events(torch)
+    torch.cuda.synchronize()
+    start.record(m.stream)
+    m.step(steps)
+    end.record(m.stream)
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end) / steps
+    sums = m.global_sums()
+    m.close()
+    nsites = 256 ** 3
+    bps = 2 * n * 19 * 4
+    return {"value": round(nsites / (ms / 1e3) / 1e6, 2), "unit": "MLUPS", "ms_per_step": round(ms, 4),
+            "species": n, "hbm_frac": round(bps * nsites / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            "algorithmic_bytes_per_site": bps, "mass": [float(x) for x in sums[:n]],
+            "note": "two kernels per step (potential pass, then the step): every population is read twice"}
+
+
 def cpu_baseline(steps: int = 5):
     """The FP64 oracle (as it stands) on `steps` steps of the full 256^3 workload."""
     import numpy as np
@@ -283,6 +311,7 @@ def main() -> int:
                                   "ms_per_step": round(ms1 / args.steps, 4),
                                   "note": "75 MB per buffer, cache-resident: HBM fraction not meaningful"}
         var["d2q9_512_replicas_batched_f32"] = batched(fm, torch, args.steps, args.warmup, plain_steps=10)
+        var["d3q19_256cube_3species_f32"] = multi_species(fm, torch, args.steps, args.warmup)
         rec["variants"] = var
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline()

@@ -304,6 +304,76 @@ fmlb_status fmlb_batch_mode_accumulate(fmlb_batch *b);
 fmlb_status fmlb_batch_mode_variances(fmlb_batch *b, int r, double *out, int64_t *n_samples);
 fmlb_status fmlb_batch_reset_modes(fmlb_batch *b);
 
+/* ------------------------------------------------------------------------
+ * N species (2..FMLB_MAX_SPECIES): the multicomponent form of the model
+ * (Apps. C and D).  Per site and species sigma:
+ *   a_sigma = -sum_s' G[sigma][s'] sum_i w_i rho_s'(r + c_i) c_i   (Eq. (87)
+ *             with one coupling per pair; G symmetric),
+ *   u = sum_sigma (j_bar_sigma + rho_sigma a_sigma / 2) / rho_t,
+ *   momentum modes relaxed with lambda_d towards rho_sigma u, with the
+ *   forcing of Eq. (72) and a noise of covariance (2 lambda_d - lambda_d^2)
+ *   k_B T (rho_sigma delta - rho_sigma rho_s' / rho_t) per component (App. D;
+ *   zero total), sampled as L z with L the Cholesky factor of the block of
+ *   species 1..N-1 (normals k D + alpha) and the last species taking minus
+ *   the sum; every other mode of species sigma as in the binary model, with
+ *   its own tau and the normals D (N - 1) + sigma (Q - D - 1) + ....  For
+ *   N = 2 this is the binary model on the same normals (same sample path up
+ *   to rounding).  Two kernels per step: an interaction-potential pass, then
+ *   the step.  Storage FMLB_F64 or FMLB_F32 (deviations from w_i rho_ref).
+ * ------------------------------------------------------------------------ */
+#define FMLB_MAX_SPECIES 4
+
+typedef struct fmlb_multi_params {
+    int32_t lattice;    /* fmlb_lattice                                             */
+    int32_t storage;    /* FMLB_F64 or FMLB_F32                                     */
+    int32_t nspecies;   /* 2 .. FMLB_MAX_SPECIES                                    */
+    int32_t nx, ny, nz; /* as fmlb_params                                           */
+    double tau[FMLB_MAX_SPECIES];  /* per species (transport and ghost modes), > 1/2 */
+    double tau_d;                  /* momentum modes of every species, > 1/2        */
+    double G[FMLB_MAX_SPECIES][FMLB_MAX_SPECIES]; /* symmetric pair couplings        */
+    double kT;                     /* >= 0                                           */
+    double rho_ref[FMLB_MAX_SPECIES]; /* reference densities of the FP32 deviations  */
+    uint64_t seed;
+    uint32_t flags;                /* FMLB_NOISE_* bits                              */
+} fmlb_multi_params;
+
+typedef struct fmlb_multi fmlb_multi;
+
+/* Bytes of buffer `which` (FMLB_BUF_*), 0 for invalid parameters: POPS_A /
+ * POPS_B: N * Q * sites * element size; SCRATCH: the potentials, FP64
+ * staging and reduction partials.  256-byte aligned buffers. */
+size_t fmlb_multi_required_bytes(const fmlb_multi_params *p, int which);
+
+/* Validate and bind three caller-owned device buffers and a HIP stream.
+ * FMLB_E_INVALID: nspecies outside 2..4, G not symmetric, storage other than
+ * F64/F32, or the conditions of fmlb_create.  The library allocates no
+ * device memory. */
+fmlb_status fmlb_multi_create(const fmlb_multi_params *p, void *hip_stream, void *const dev_buf[3],
+                              fmlb_multi **out);
+void fmlb_multi_destroy(fmlb_multi *m);
+
+/* Rest state f_bar_i = w_i rho[sigma][site] from host FP64 densities
+ * rho[N][sites]; step counter 0.  Synchronises. */
+fmlb_status fmlb_multi_init_density(fmlb_multi *m, const double *rho);
+
+/* Advance n >= 0 steps (asynchronous).  FMLB_E_STATE before an initial state. */
+fmlb_status fmlb_multi_step(fmlb_multi *m, int64_t n);
+int64_t fmlb_multi_current_step(const fmlb_multi *m);
+
+/* Pre-collision populations f_bar[N][Q][sites] (FP64, absolute) to / from
+ * host memory (bytes >= 8 N Q sites); set also sets the step counter.
+ * Synchronise. */
+fmlb_status fmlb_multi_get_populations(fmlb_multi *m, double *host, size_t bytes);
+fmlb_status fmlb_multi_set_populations(fmlb_multi *m, const double *host, size_t bytes, int64_t step);
+
+/* rho[N][sites] and j_bar[N][D][sites] (FP64) of the current state; either
+ * may be NULL.  Synchronises. */
+fmlb_status fmlb_multi_moments(fmlb_multi *m, double *rho, double *j);
+
+/* out[sigma] = sum rho_sigma (sigma < N), out[N + alpha] = total momentum
+ * sum_sigma j_bar_sigma,alpha (alpha < D); FP64.  Synchronises. */
+fmlb_status fmlb_multi_global_sums(fmlb_multi *m, double *out);
+
 #ifdef __cplusplus
 }
 #endif

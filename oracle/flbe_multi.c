@@ -188,7 +188,8 @@ static void multi_acceleration(const orc_multi *s, int64_t r, double a[ORC_MAX_S
 }
 
 /* Lower Cholesky factor of the n x n symmetric positive-definite A (row
- * major, leading dimension ORC_MAX_SPECIES). */
+ * major, leading dimension ORC_MAX_SPECIES).  A pivot that rounds to <= 0
+ * (a density far below the others) gives a zero column instead of a NaN. */
 static void cholesky(int n, const double A[ORC_MAX_SPECIES][ORC_MAX_SPECIES],
                      double L[ORC_MAX_SPECIES][ORC_MAX_SPECIES])
 {
@@ -198,7 +199,10 @@ static void cholesky(int n, const double A[ORC_MAX_SPECIES][ORC_MAX_SPECIES],
         for (int k = 0; k <= i; ++k) {
             double sum = A[i][k];
             for (int m = 0; m < k; ++m) sum -= L[i][m] * L[k][m];
-            L[i][k] = (i == k) ? sqrt(sum) : sum / L[k][k];
+            if (i == k)
+                L[i][k] = sum > 0.0 ? sqrt(sum) : 0.0;
+            else
+                L[i][k] = L[k][k] > 0.0 ? sum / L[k][k] : 0.0;
         }
 }
 

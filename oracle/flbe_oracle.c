@@ -258,7 +258,11 @@ void orc_uniforms(uint64_t seed, uint32_t site, int64_t step, int n, double *u)
  *               z_2p+1 = sqrt(-2 ln u_2p) sin(2 pi u_2p+1). */
 void orc_normals(uint64_t seed, uint32_t site, int64_t step, int K, double *z)
 {
-    double u[64];
+    double u[128]; /* up to 128 normals: D3Q19 with 4 species needs 69 */
+    if (K > 128) {
+        for (int k = 0; k < K; ++k) z[k] = NAN;
+        return;
+    }
     const int pairs = (K + 1) / 2;
     orc_uniforms(seed, site, step, 2 * pairs, u);
     const double two_pi = 6.283185307179586476925286766559;

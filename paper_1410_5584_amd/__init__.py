@@ -42,6 +42,18 @@ class fmlb_params(ctypes.Structure):
                 ("rho_ref", ctypes.c_double * 2), ("seed", ctypes.c_uint64), ("flags", ctypes.c_uint32)]
 
 
+FMLB_MAX_SPECIES = 4
+
+
+class fmlb_multi_params(ctypes.Structure):
+    _fields_ = [("lattice", ctypes.c_int32), ("storage", ctypes.c_int32), ("nspecies", ctypes.c_int32),
+                ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("tau", ctypes.c_double * FMLB_MAX_SPECIES), ("tau_d", ctypes.c_double),
+                ("G", (ctypes.c_double * FMLB_MAX_SPECIES) * FMLB_MAX_SPECIES), ("kT", ctypes.c_double),
+                ("rho_ref", ctypes.c_double * FMLB_MAX_SPECIES), ("seed", ctypes.c_uint64),
+                ("flags", ctypes.c_uint32)]
+
+
 class FmlbError(RuntimeError):
     def __init__(self, fn: str, status: int):
         msg = lib().fmlb_status_string(status).decode()
@@ -56,6 +68,7 @@ _vp = ctypes.c_void_p
 _dp = ctypes.POINTER(ctypes.c_double)
 _i64p = ctypes.POINTER(ctypes.c_int64)
 _pp = ctypes.POINTER(fmlb_params)
+_mpp = ctypes.POINTER(fmlb_multi_params)
 
 _SIGNATURES = {
     "fmlb_required_bytes": (ctypes.c_size_t, [_pp, ctypes.c_int]),
@@ -96,6 +109,16 @@ _SIGNATURES = {
     "fmlb_batch_size": (ctypes.c_int, [_vp]),
     "fmlb_batch_total_sites": (ctypes.c_int64, [_vp]),
     "fmlb_batch_current_step": (ctypes.c_int64, [_vp]),
+    "fmlb_multi_required_bytes": (ctypes.c_size_t, [_mpp, ctypes.c_int]),
+    "fmlb_multi_create": (ctypes.c_int32, [_mpp, _vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp)]),
+    "fmlb_multi_destroy": (None, [_vp]),
+    "fmlb_multi_init_density": (ctypes.c_int32, [_vp, _dp]),
+    "fmlb_multi_step": (ctypes.c_int32, [_vp, ctypes.c_int64]),
+    "fmlb_multi_current_step": (ctypes.c_int64, [_vp]),
+    "fmlb_multi_get_populations": (ctypes.c_int32, [_vp, _dp, ctypes.c_size_t]),
+    "fmlb_multi_set_populations": (ctypes.c_int32, [_vp, _dp, ctypes.c_size_t, ctypes.c_int64]),
+    "fmlb_multi_moments": (ctypes.c_int32, [_vp, _dp, _dp]),
+    "fmlb_multi_global_sums": (ctypes.c_int32, [_vp, _dp]),
 }
 
 
@@ -314,6 +337,52 @@ def fmlb_copy_reference(ctx: int):
 
 # ---- convenience wrapper: torch-owned buffers, numpy host arrays ------------
 
+def fmlb_multi_required_bytes(p: fmlb_multi_params, which: int) -> int:
+    return lib().fmlb_multi_required_bytes(ctypes.byref(p), which)
+
+
+def fmlb_multi_create(p: fmlb_multi_params, stream: int, bufs) -> int:
+    arr = (_vp * 3)(*[_vp(int(b)) for b in bufs])
+    out = _vp()
+    _check("fmlb_multi_create", lib().fmlb_multi_create(ctypes.byref(p), _vp(stream), arr, ctypes.byref(out)))
+    return out.value
+
+
+def fmlb_multi_destroy(m: int):
+    lib().fmlb_multi_destroy(_vp(m))
+
+
+def fmlb_multi_init_density(m: int, rho: np.ndarray):
+    r = _f64(rho)
+    _check("fmlb_multi_init_density", lib().fmlb_multi_init_density(_vp(m), _ptr(r)))
+
+
+def fmlb_multi_step(m: int, n: int):
+    _check("fmlb_multi_step", lib().fmlb_multi_step(_vp(m), int(n)))
+
+
+def fmlb_multi_current_step(m: int) -> int:
+    return lib().fmlb_multi_current_step(_vp(m))
+
+
+def fmlb_multi_get_populations(m: int, out: np.ndarray):
+    _check("fmlb_multi_get_populations", lib().fmlb_multi_get_populations(_vp(m), _ptr(out), out.nbytes))
+
+
+def fmlb_multi_set_populations(m: int, f: np.ndarray, step: int):
+    f = _f64(f)
+    _check("fmlb_multi_set_populations", lib().fmlb_multi_set_populations(_vp(m), _ptr(f), f.nbytes, int(step)))
+
+
+def fmlb_multi_moments(m: int, rho: np.ndarray | None, j: np.ndarray | None):
+    _check("fmlb_multi_moments", lib().fmlb_multi_moments(_vp(m), _ptr(rho) if rho is not None else None,
+                                                          _ptr(j) if j is not None else None))
+
+
+def fmlb_multi_global_sums(m: int, out: np.ndarray):
+    _check("fmlb_multi_global_sums", lib().fmlb_multi_global_sums(_vp(m), _ptr(out)))
+
+
 @dataclass
 class Params:
     lattice: str = "d2q9"
@@ -518,6 +587,106 @@ class Batch:
 
     def reset_modes(self):
         fmlb_batch_reset_modes(self.b)
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+
+@dataclass
+class MultiParams:
+    """N species (2..4), the multicomponent model; G: symmetric N x N pair
+    couplings."""
+    lattice: str = "d2q9"
+    storage: str = "f64"
+    nspecies: int = 3
+    nx: int = 32
+    ny: int = 32
+    nz: int = 1
+    tau: tuple = (1.0, 1.0, 1.0)
+    tau_d: float = 1.0
+    G: tuple = ((0.0, 0.0, 0.0), (0.0, 0.0, 0.0), (0.0, 0.0, 0.0))
+    kT: float = 0.0
+    rho_ref: tuple = (1.0, 1.0, 1.0)
+    seed: int = 1
+    flags: int = 0
+
+    def c(self) -> fmlb_multi_params:
+        n = self.nspecies  # passed as given: the library rejects values outside 2..4
+        M = FMLB_MAX_SPECIES
+        k = max(0, min(n, M))
+        G = ((ctypes.c_double * M) * M)()
+        for a in range(k):
+            for b in range(k):
+                G[a][b] = float(self.G[a][b])
+        pad = lambda t, v: (ctypes.c_double * M)(*(list(t)[:k] + [v] * (M - min(len(t), k))))
+        return fmlb_multi_params(LATTICES[self.lattice], STORAGES[self.storage], n, self.nx, self.ny, self.nz,
+                                 pad(self.tau, 1.0), self.tau_d, G, self.kT, pad(self.rho_ref, 0.0), self.seed,
+                                 self.flags)
+
+
+class Multi:
+    """One N-species lattice on the current device (torch-owned buffers,
+    torch's current stream)."""
+
+    def __init__(self, p: MultiParams, device=None, stream=None):
+        import torch
+        self.p = p
+        cp = p.c()
+        sizes = [fmlb_multi_required_bytes(cp, k) for k in range(3)]
+        if min(sizes) == 0:
+            raise FmlbError("fmlb_multi_required_bytes", FMLB_E_INVALID)
+        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.bufs = [torch.empty(s, dtype=torch.uint8, device=dev) for s in sizes]
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        self.m = fmlb_multi_create(cp, self.stream.cuda_stream, [b.data_ptr() for b in self.bufs])
+        self.N = p.nspecies
+        self.Q = 9 if p.lattice == "d2q9" else 19
+        self.D = 2 if p.lattice == "d2q9" else 3
+        self.shape = (p.nz, p.ny, p.nx)
+        self.nsites = p.nx * p.ny * p.nz
+
+    def close(self):
+        if getattr(self, "m", None):
+            fmlb_multi_destroy(self.m)
+            self.m = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # interpreter shutdown: the library may already be gone
+            pass
+
+    @property
+    def step_count(self) -> int:
+        return fmlb_multi_current_step(self.m)
+
+    def init_density(self, rho):
+        """rho: N scalars or arrays of the lattice shape."""
+        if len(rho) != self.N:
+            raise ValueError(f"{len(rho)} density fields for {self.N} species")
+        fmlb_multi_init_density(self.m, np.stack([_as_field(r, self.shape) for r in rho]))
+
+    def step(self, n: int = 1):
+        fmlb_multi_step(self.m, n)
+
+    def populations(self):
+        out = np.empty((self.N, self.Q) + self.shape)
+        fmlb_multi_get_populations(self.m, out)
+        return out
+
+    def set_populations(self, f, step: int = 0):
+        fmlb_multi_set_populations(self.m, np.asarray(f, dtype=np.float64).reshape(self.N, self.Q, *self.shape), step)
+
+    def moments(self):
+        rho = np.empty((self.N,) + self.shape)
+        j = np.empty((self.N, self.D) + self.shape)
+        fmlb_multi_moments(self.m, rho, j)
+        return rho, j
+
+    def global_sums(self):
+        out = np.empty(self.N + self.D)
+        fmlb_multi_global_sums(self.m, out)
+        return out
 
     def synchronize(self):
         self.stream.synchronize()

@@ -343,21 +343,24 @@ __device__ __forceinline__ Real relax_add(int i, Real base, Real x)
     }
 }
 
-// Collision of species s at one site, in place.  zmom: the D momentum
-// normals; zmode: the NS normals of this species' non-hydrodynamic modes.
+// Collision of one species at one site, in place: f holds the deviations
+// d_i = f_i - w_i ref (see collide_site), r the absolute density, dr = r -
+// ref, js the momentum, a the acceleration, F = r a, u the common
+// equilibrium velocity, lam / lam_d / gain the species' rates and noise
+// gain sqrt((2 lambda - lambda^2) mu).  The momentum noise is amp * zmom
+// (binary model: +-sigma_d times the D momentum normals; N species: amp = 1
+// and zmom the species' correlated noise); zmode holds the NS normals of the
+// species' non-hydrodynamic modes.
 template <class L, class Real>
-__device__ __forceinline__ void collide_species(int s, Real (&f)[L::Q], Real r, Real dr, const Real (&js)[3],
-                                                const Real (&a)[3], const SiteCommon<Real> &c,
-                                                const Phys<Real> &ph, const Real *zmom, const Real *zmode)
+__device__ __forceinline__ void relax_species(Real (&f)[L::Q], Real r, Real dr, const Real (&js)[3],
+                                              const Real (&a)[3], const Real (&F)[3], const Real (&u)[3], Real lam,
+                                              Real lam_d, Real gain, Real amp, const Real *zmom, const Real *zmode)
 {
     constexpr int Q = L::Q, D = L::D;
-    const Real lam = ph.lam[s];
-    const Real sgn_sd = s == 0 ? c.sd : -c.sd;
     Real R[3] = {0, 0, 0}, v[3] = {0, 0, 0};
 #pragma unroll
     for (int al = 0; al < D; ++al)
-        R[al] = ph.lam_d * (r * c.u[al] - js[al]) + (Real(1) - Real(0.5) * ph.lam_d) * c.F[s][al] +
-                sgn_sd * zmom[al];
+        R[al] = lam_d * (r * u[al] - js[al]) + (Real(1) - Real(0.5) * lam_d) * F[al] + amp * zmom[al];
     if (r > Real(0)) {
         const Real inv_r = rcp(r);
 #pragma unroll
@@ -366,7 +369,7 @@ __device__ __forceinline__ void collide_species(int s, Real (&f)[L::Q], Real r, 
 
     // non-hydrodynamic mode noise, zs[a] = g z_a / sqrt(N_a)
     Real zs[Q];
-    const Real g = r > Real(0) ? ph.gain[s] * root(r) : Real(0);
+    const Real g = r > Real(0) ? gain * root(r) : Real(0);
 #pragma unroll
     for (int q = 0; q < Q; ++q) zs[q] = 0;
 #pragma unroll
@@ -375,7 +378,6 @@ __device__ __forceinline__ void collide_species(int s, Real (&f)[L::Q], Real r, 
     mn.init(zs);
 
     // M = 9/2 P + N, P = lambda rho u u + (1 - lambda/2) rho (a v + v a)
-    const Real *u = c.u;
     const Real lr = lam * r;
     const Real cf = (Real(1) - Real(0.5) * lam) * r;
     auto Pc = [&](int al, int be) { return lr * u[al] * u[be] + cf * (a[al] * v[be] + v[al] * a[be]); };
@@ -416,6 +418,18 @@ __device__ __forceinline__ void collide_species(int s, Real (&f)[L::Q], Real r, 
         f[i] = relax_add<L>(i, keep * f[i], E + O);
         f[ib] = relax_add<L>(ib, keep * f[ib], E - O);
     }
+}
+
+// Collision of species s of the binary model at one site, in place.  zmom:
+// the D momentum normals (noise +sigma_d z for species 1, -sigma_d z for
+// species 2, Eq. (74)); zmode: the NS normals of this species' modes.
+template <class L, class Real>
+__device__ __forceinline__ void collide_species(int s, Real (&f)[L::Q], Real r, Real dr, const Real (&js)[3],
+                                                const Real (&a)[3], const SiteCommon<Real> &c,
+                                                const Phys<Real> &ph, const Real *zmom, const Real *zmode)
+{
+    relax_species<L, Real>(f, r, dr, js, a, c.F[s], c.u, ph.lam[s], ph.lam_d, ph.gain[s], s == 0 ? c.sd : -c.sd,
+                           zmom, zmode);
 }
 
 // Collide both species at one site in place, species 1 first.  f holds the

@@ -1,0 +1,314 @@
+// N species (2..4): the multicomponent form of the model (Apps. C and D).
+//
+// Per site and species sigma, with the densities of the same step:
+//   a_sigma = -sum_s' G_sigma,s' sum_i w_i rho_s'(r + c_i) c_i   (Eq. (87), one coupling per pair)
+//   u       = sum_sigma (j_bar_sigma + rho_sigma a_sigma / 2) / rho_t
+//   momentum noise xi_sigma with covariance (2 lambda_d - lambda_d^2) k_B T
+//   (rho_sigma delta_sigma,s' - rho_sigma rho_s' / rho_t) per component (App. D,
+//   with the lattice factor of Eq. (74)); every row sums to zero, so the
+//   total momentum receives none.  It is sampled with the Cholesky factor L
+//   of the block of species 1..N-1 (positive definite when every density is
+//   positive): xi_sigma,alpha = sum_k L_sigma,k z_(k D + alpha) for sigma < N,
+//   and xi_N = -(xi_1 + ... + xi_(N-1)).  For N = 2 this is the binary
+//   model's +-sigma_d z on the same normals.
+//   The non-momentum modes of species sigma use normals D (N - 1) + sigma NS + ...
+//   and relax as in the binary model (relax_species).
+//
+// Two passes per step: the first pulls every population and writes the
+// interaction potential phi_sigma = sum_s' G_sigma,s' (rho_s' - rho_ref,s')
+// per site (the force needs only differences, sum_i w_i c_i = 0); the second
+// pulls again, collides and stores.  Storage FP64 (absolute) or FP32
+// (deviations from w_i rho_ref, as in the binary FP32 path).
+#pragma once
+
+#include "kernels.h"
+
+namespace fmlb {
+
+constexpr int kMaxSpecies = 4;
+
+template <class Real>
+struct MultiPhys {
+    Real lam[kMaxSpecies];   // 1 / tau_sigma
+    Real lam_d;              // 1 / tau_d
+    Real gain[kMaxSpecies];  // sqrt((2 lambda - lambda^2) mu), 0 without noise
+    Real sd2;                // (2 lambda_d - lambda_d^2) k_B T, 0 without momentum noise
+    Real G[kMaxSpecies][kMaxSpecies];
+    Real ref[kMaxSpecies];   // rho_ref of the stored deviations (0 for FP64)
+    uint32_t key0, key1;
+};
+
+template <class S>
+struct MultiArgs {
+    using Real = typename Storage<S>::Real;
+    const S *src;
+    S *dst;
+    Real *phi;  // [N][sites]
+    Geom g;
+    MultiPhys<Real> ph;
+    uint32_t step_lo, step_hi;
+};
+
+// The stored values of the N Q pulled populations of site (x, y, z).
+template <class L, class S, int N>
+__device__ __forceinline__ void multi_pull(const S *src, const Geom &g, int x, int y, int z,
+                                           typename Storage<S>::Real (&f)[N][L::Q])
+{
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        const int xs = wrap(x, -L::cx[i], g.nx);
+        const int ys = wrap(y, -L::cy[i], g.ny);
+        const int zs = L::D == 3 ? wrap(z, -L::cz[i], g.nz) : 0;
+        const size_t site = (size_t)xs + (size_t)g.nx * ((size_t)ys + (size_t)g.ny * (size_t)zs);
+#pragma unroll
+        for (int s = 0; s < N; ++s) f[s][i] = Storage<S>::load(src, ((size_t)(s * L::Q + i)) * g.nsites + site);
+    }
+}
+
+template <class L, class S, int N>
+__global__ __launch_bounds__(256) void multi_potential_kernel(MultiArgs<S> a)
+{
+    using Real = typename Storage<S>::Real;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y, z = blockIdx.z;
+    if (x >= a.g.nx) return;
+    Real f[N][L::Q];
+    multi_pull<L, S, N>(a.src, a.g, x, y, z, f);
+    Real dr[N];
+#pragma unroll
+    for (int s = 0; s < N; ++s) {
+        Real j[3];
+        moments<L, Real>(f[s], dr[s], j);
+    }
+    const size_t site = (size_t)x + (size_t)a.g.nx * ((size_t)y + (size_t)a.g.ny * (size_t)z);
+#pragma unroll
+    for (int s = 0; s < N; ++s) {
+        Real v = 0;
+#pragma unroll
+        for (int t = 0; t < N; ++t) v += a.ph.G[s][t] * dr[t];
+        a.phi[(size_t)s * a.g.nsites + site] = v;
+    }
+}
+
+// Momentum noise xi[N][3] of one site from the normals z[0 .. D(N-1)-1].
+template <class L, class Real, int N>
+__device__ __forceinline__ void multi_momentum_noise(const Real (&rho)[N], Real rt, Real sd2, const Real *z,
+                                                     Real (&xi)[N][3])
+{
+    constexpr int D = L::D;
+#pragma unroll
+    for (int s = 0; s < N; ++s) xi[s][0] = xi[s][1] = xi[s][2] = 0;
+    bool positive = rt > Real(0);
+#pragma unroll
+    for (int s = 0; s < N; ++s) positive = positive && rho[s] > Real(0);
+    if (!positive) return;
+    // covariance block of species 0..N-2 and its lower Cholesky factor
+    const Real inv_rt = rcp(rt);
+    Real C[N - 1][N - 1], Lc[N - 1][N - 1];
+#pragma unroll
+    for (int p = 0; p < N - 1; ++p)
+#pragma unroll
+        for (int q = 0; q < N - 1; ++q) C[p][q] = sd2 * ((p == q ? rho[p] : Real(0)) - rho[p] * rho[q] * inv_rt);
+#pragma unroll
+    for (int p = 0; p < N - 1; ++p)
+#pragma unroll
+        for (int q = 0; q < N - 1; ++q) Lc[p][q] = 0;
+#pragma unroll
+    for (int p = 0; p < N - 1; ++p) {
+#pragma unroll
+        for (int q = 0; q <= p; ++q) {
+            Real acc = C[p][q];
+#pragma unroll
+            for (int m = 0; m < q; ++m) acc -= Lc[p][m] * Lc[q][m];
+            if (q == p)
+                Lc[p][p] = acc > Real(0) ? root(acc) : Real(0);
+            else
+                Lc[p][q] = Lc[q][q] > Real(0) ? acc * rcp(Lc[q][q]) : Real(0);
+        }
+    }
+#pragma unroll
+    for (int al = 0; al < D; ++al) {
+        Real total = 0;
+#pragma unroll
+        for (int p = 0; p < N - 1; ++p) {
+            Real v = 0;
+#pragma unroll
+            for (int k = 0; k <= p; ++k) v += Lc[p][k] * z[k * D + al];
+            xi[p][al] = v;
+            total += v;
+        }
+        xi[N - 1][al] = -total;
+    }
+}
+
+template <class L, class S, int N>
+__global__ __launch_bounds__(256) void multi_step_kernel(MultiArgs<S> a)
+{
+    using Real = typename Storage<S>::Real;
+    constexpr int Q = L::Q, D = L::D, NS = Q - D - 1;
+    constexpr int K = D * (N - 1) + N * NS;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y, z = blockIdx.z;
+    if (x >= a.g.nx) return;
+    const Geom g = a.g;
+    const MultiPhys<Real> &ph = a.ph;
+    Real f[N][Q];
+    multi_pull<L, S, N>(a.src, g, x, y, z, f);
+
+    // force from the neighbours' potentials: a_sigma = -sum_i w_i c_i phi_sigma(r + c_i)
+    Real acc[N][3];
+#pragma unroll
+    for (int s = 0; s < N; ++s) {
+        Real ax = 0, ay = 0, az = 0;
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+            const int xn = wrap(x, L::cx[i], g.nx);
+            const int yn = wrap(y, L::cy[i], g.ny);
+            const int zn = D == 3 ? wrap(z, L::cz[i], g.nz) : 0;
+            const Real t = Real(L::w36[i]) / Real(36) *
+                           a.phi[(size_t)s * g.nsites + (size_t)xn + (size_t)g.nx * ((size_t)yn + (size_t)g.ny * zn)];
+            if (L::cx[i]) ax += L::cx[i] > 0 ? t : -t;
+            if (L::cy[i]) ay += L::cy[i] > 0 ? t : -t;
+            if (D == 3 && L::cz[i]) az += L::cz[i] > 0 ? t : -t;
+        }
+        acc[s][0] = -ax;
+        acc[s][1] = -ay;
+        acc[s][2] = -az;
+    }
+
+    Real dr[N], rho[N], j[N][3], F[N][3];
+    Real rt = 0;
+#pragma unroll
+    for (int s = 0; s < N; ++s) {
+        moments<L, Real>(f[s], dr[s], j[s]);
+        rho[s] = ph.ref[s] + dr[s];
+        rt += rho[s];
+#pragma unroll
+        for (int al = 0; al < 3; ++al) F[s][al] = rho[s] * acc[s][al];
+    }
+    Real u[3] = {0, 0, 0};
+    if (rt > Real(0)) {
+        const Real inv_rt = rcp(rt);
+#pragma unroll
+        for (int al = 0; al < D; ++al) {
+            Real jt = 0, Ft = 0;
+#pragma unroll
+            for (int s = 0; s < N; ++s) {
+                jt += j[s][al];
+                Ft += F[s][al];
+            }
+            u[al] = jt * inv_rt + Real(0.5) * (Ft * inv_rt);
+        }
+    }
+
+    // every normal of the site, in stream order (word w: normals 2w, 2w + 1)
+    const size_t site = (size_t)x + (size_t)g.nx * ((size_t)y + (size_t)g.ny * (size_t)z);
+    const Counter ctr{(uint32_t)site, a.step_lo, a.step_hi};
+    Real znorm[K + 1];
+#pragma unroll
+    for (int b = 0; b < (K + 7) / 8; ++b) {
+        uint32_t w[4];
+        block_words(ctr, (uint32_t)b, ph.key0, ph.key1, w);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int k = 2 * (4 * b + t);
+            if (k < K) word_normals<Real>(w[t], znorm[k], znorm[k + 1]);
+        }
+    }
+    Real xi[N][3];
+    multi_momentum_noise<L, Real, N>(rho, rt, ph.sd2, znorm, xi);
+
+#pragma unroll
+    for (int s = 0; s < N; ++s) {
+        relax_species<L, Real>(f[s], rho[s], dr[s], j[s], acc[s], F[s], u, ph.lam[s], ph.lam_d, ph.gain[s], Real(1),
+                               xi[s], znorm + D * (N - 1) + s * NS);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) Storage<S>::store(a.dst, ((size_t)(s * Q + i)) * g.nsites + site, f[s][i]);
+    }
+}
+
+// Rest state of species s: buf_i(r) = w_i rho(r + c_i) - w_i ref (pull layout).
+template <class L, class S>
+__global__ __launch_bounds__(256) void multi_init_kernel(S *dst, const double *rho, Geom g, int s, double ref)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y, z = blockIdx.z;
+    if (x >= g.nx) return;
+    const size_t site = (size_t)x + (size_t)g.nx * ((size_t)y + (size_t)g.ny * (size_t)z);
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        const int xn = wrap(x, L::cx[i], g.nx);
+        const int yn = wrap(y, L::cy[i], g.ny);
+        const int zn = L::D == 3 ? wrap(z, L::cz[i], g.nz) : 0;
+        const size_t nsite = (size_t)xn + (size_t)g.nx * ((size_t)yn + (size_t)g.ny * (size_t)zn);
+        store_pop_f64<L, S>(dst, g.nsites, s, i, site, (double)L::w36[i] / 36.0 * rho[nsite], ref);
+    }
+}
+
+// FP64 rho_s and j_bar_s (D components) of the pre-collision state into
+// out[0][sites], out[1 + alpha][sites].
+template <class L, class S>
+__global__ __launch_bounds__(256) void multi_moment_kernel(const S *src, double *out, Geom g, int s, double ref)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y, z = blockIdx.z;
+    if (x >= g.nx) return;
+    double r = 0, j[3] = {0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        const int xs = wrap(x, -L::cx[i], g.nx);
+        const int ys = wrap(y, -L::cy[i], g.ny);
+        const int zs = L::D == 3 ? wrap(z, -L::cz[i], g.nz) : 0;
+        const size_t from = (size_t)xs + (size_t)g.nx * ((size_t)ys + (size_t)g.ny * (size_t)zs);
+        const double v = load_pop_f64<L, S>(src, g.nsites, s, i, from, ref);
+        r += v;
+        if (L::cx[i]) j[0] += L::cx[i] > 0 ? v : -v;
+        if (L::cy[i]) j[1] += L::cy[i] > 0 ? v : -v;
+        if (L::D == 3 && L::cz[i]) j[2] += L::cz[i] > 0 ? v : -v;
+    }
+    const size_t site = (size_t)x + (size_t)g.nx * ((size_t)y + (size_t)g.ny * (size_t)z);
+    out[site] = r;
+#pragma unroll
+    for (int al = 0; al < L::D; ++al) out[(size_t)(1 + al) * g.nsites + site] = j[al];
+}
+
+// Block partial sums (FP64) of rho_s and j_bar_s over the sites:
+// partial[block][0] = sum rho, partial[block][1 + alpha] = sum j_alpha.
+template <class L, class S>
+__global__ __launch_bounds__(256) void multi_sums_kernel(const S *src, double *partial, Geom g, int s, double ref)
+{
+    __shared__ double red[4][256];
+    double v[4] = {0, 0, 0, 0};
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < g.nsites; t += (size_t)gridDim.x * blockDim.x) {
+        const int x = (int)(t % (size_t)g.nx);
+        const size_t rr = t / (size_t)g.nx;
+        const int y = (int)(rr % (size_t)g.ny);
+        const int z = (int)(rr / (size_t)g.ny);
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) {
+            const int xs = wrap(x, -L::cx[i], g.nx);
+            const int ys = wrap(y, -L::cy[i], g.ny);
+            const int zs = L::D == 3 ? wrap(z, -L::cz[i], g.nz) : 0;
+            const size_t from = (size_t)xs + (size_t)g.nx * ((size_t)ys + (size_t)g.ny * (size_t)zs);
+            const double f = load_pop_f64<L, S>(src, g.nsites, s, i, from, ref);
+            v[0] += f;
+            if (L::cx[i]) v[1] += L::cx[i] > 0 ? f : -f;
+            if (L::cy[i]) v[2] += L::cy[i] > 0 ? f : -f;
+            if (L::D == 3 && L::cz[i]) v[3] += L::cz[i] > 0 ? f : -f;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) red[q][threadIdx.x] = v[q];
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) partial[(size_t)blockIdx.x * 4 + q] = red[q][0];
+}
+
+}  // namespace fmlb

@@ -104,3 +104,32 @@ def test_batch_invalid_replica_rejected(fm, bad):
     with pytest.raises(fm.FmlbError) as e:
         fm.fmlb_batch_create([_rep(fm)], 0, [256, 0, 768])
     assert e.value.status == fm.FMLB_E_NULL
+
+
+def test_multi_required_bytes(fm):
+    G = ((0.0, 0.3, 0.2), (0.3, 0.0, 0.1), (0.2, 0.1, 0.0))
+    p = fm.MultiParams(lattice="d3q19", storage="f32", nspecies=3, nx=64, ny=32, nz=16, G=G)
+    n = 64 * 32 * 16
+    assert fm.fmlb_multi_required_bytes(p.c(), 0) == 3 * 19 * n * 4
+    assert fm.fmlb_multi_required_bytes(p.c(), 1) == 3 * 19 * n * 4
+    assert fm.fmlb_multi_required_bytes(p.c(), 2) >= 3 * n * 4 + 4 * n * 8
+    p4 = fm.MultiParams(lattice="d2q9", storage="f64", nspecies=4, nx=10, ny=10, tau=(1.0,) * 4,
+                        G=tuple((0.0,) * 4 for _ in range(4)))
+    assert fm.fmlb_multi_required_bytes(p4.c(), 0) == 4 * 9 * 100 * 8 + (256 - (4 * 9 * 100 * 8) % 256) % 256
+
+
+@pytest.mark.parametrize("bad", [
+    dict(nspecies=1), dict(nspecies=5), dict(storage="bf16"), dict(tau=(1.0, 0.5, 1.0)),
+    dict(G=((0.0, 0.3, 0.2), (0.31, 0.0, 0.1), (0.2, 0.1, 0.0))), dict(lattice="d2q9", nz=2), dict(kT=-1.0),
+])
+def test_multi_invalid_parameters_rejected(fm, bad):
+    kw = dict(nspecies=3, G=((0.0, 0.3, 0.2), (0.3, 0.0, 0.1), (0.2, 0.1, 0.0)))
+    kw.update(bad)
+    if kw["nspecies"] in (1, 5):
+        kw["G"] = tuple((0.0,) * 4 for _ in range(4))
+    p = fm.MultiParams(**kw)
+    for which in range(3):
+        assert fm.fmlb_multi_required_bytes(p.c(), which) == 0
+    with pytest.raises(fm.FmlbError) as e:
+        fm.fmlb_multi_create(p.c(), 0, [256, 512, 768])
+    assert e.value.status == fm.FMLB_E_INVALID

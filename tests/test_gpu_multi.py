@@ -1,0 +1,170 @@
+"""N-species path (Apps. C and D) on the GPU against the N-species oracle.
+
+- FP64 sample-path parity at 1e-12 for N = 2, 3, 4 on D2Q9 and D3Q19 (ragged
+  sizes, a full coupling matrix, species-dependent tau, noise on / off /
+  without momentum noise); FP32 (deviation storage) at 2e-5.
+- N = 2 is the binary model: the N-species kernels reproduce the binary
+  path's populations (FP64, rounding-level differences only).
+- Conservation of every species' mass and of the total momentum.
+- The ideal mixture (G = 0, N = 3) is equipartitioned at every site:
+  <j_sigma j_s'> = k_B T rho_sigma delta, <drho_sigma drho_s'> = 3 k_B T rho_sigma delta.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+G3 = ((0.0, 0.45, 0.3), (0.45, 0.0, 0.6), (0.3, 0.6, 0.0))
+G4 = ((0.0, 0.45, 0.3, 0.2), (0.45, 0.0, 0.6, 0.1), (0.3, 0.6, 0.0, 0.5), (0.2, 0.1, 0.5, 0.0))
+
+
+@pytest.fixture(scope="module")
+def fm():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1410_5584_amd as fm
+    fm.lib()
+    return fm
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _couplings(n):
+    return {2: ((0.0, 0.7), (0.7, 0.0)), 3: G3, 4: G4}[n]
+
+
+def _densities(shape, n, seed=1):
+    import workloads
+    return [workloads.initial_density(shape, "perturbed", seed=seed + s, amplitude=0.05)[0] * (1.0 - 0.2 * s)
+            for s in range(n)]
+
+
+def _pair(fm, lattice, shape, n, storage, kT=1e-4, flags=0, seed=4):
+    import oracle
+    nz, ny, nx = shape
+    tau = (0.8, 1.1, 1.3, 0.9)[:n]
+    G = _couplings(n)
+    g = fm.Multi(fm.MultiParams(lattice=lattice, storage=storage, nspecies=n, nx=nx, ny=ny, nz=nz, tau=tau,
+                                tau_d=0.9, G=G, kT=kT, rho_ref=(1.0, 0.8, 0.6, 0.4)[:n], seed=seed, flags=flags))
+    o = oracle.MultiSim(oracle.MultiParams(lattice={"d2q9": oracle.D2Q9, "d3q19": oracle.D3Q19}[lattice],
+                                           nspecies=n, nx=nx, ny=ny, nz=nz, tau=tau, tau_d=0.9, G=G, kT=kT,
+                                           seed=seed, flags=flags))
+    rho = _densities(shape, n)
+    g.init_density(rho)
+    o.init_density(rho)
+    return g, o
+
+
+CASES = [("d2q9", (1, 9, 13), 2), ("d2q9", (1, 9, 13), 3), ("d2q9", (1, 12, 70), 4),
+         ("d3q19", (5, 6, 7), 2), ("d3q19", (5, 6, 7), 3), ("d3q19", (4, 5, 66), 4)]
+
+
+@pytest.mark.parametrize("lattice,shape,n", CASES)
+def test_multi_parity_fp64(fm, lattice, shape, n):
+    _say("case multi fp64", lattice, shape, n)
+    g, o = _pair(fm, lattice, shape, n, "f64")
+    g.step(20)
+    o.step(20)
+    fg, fo = g.populations(), o.populations()
+    err = np.max(np.abs(fg - fo)) / np.max(np.abs(fo))
+    _say("  max rel diff", err)
+    assert err <= 1e-12
+    g.close()
+
+
+@pytest.mark.parametrize("flags", [1, 2])
+def test_multi_parity_fp64_noise_flags(fm, flags):
+    _say("case multi fp64 flags", flags)
+    g, o = _pair(fm, "d2q9", (1, 11, 10), 3, "f64", flags=flags)
+    g.step(30)
+    o.step(30)
+    fg, fo = g.populations(), o.populations()
+    assert np.max(np.abs(fg - fo)) <= 1e-12 * np.max(np.abs(fo))
+    g.close()
+
+
+@pytest.mark.parametrize("lattice,shape,n", CASES)
+def test_multi_parity_fp32(fm, lattice, shape, n):
+    _say("case multi fp32", lattice, shape, n)
+    g, o = _pair(fm, lattice, shape, n, "f32")
+    g.step(20)
+    o.step(20)
+    fg, fo = g.populations(), o.populations()
+    err = np.max(np.abs(fg - fo)) / np.max(np.abs(fo))
+    _say("  max rel diff", err)
+    assert err <= 2e-5
+    g.close()
+
+
+@pytest.mark.parametrize("lattice,shape", [("d2q9", (1, 17, 23)), ("d3q19", (6, 5, 9))])
+def test_two_species_kernels_match_the_binary_path(fm, lattice, shape):
+    _say("case multi N=2 vs binary", lattice, shape)
+    nz, ny, nx = shape
+    kw = dict(lattice=lattice, storage="f64", nx=nx, ny=ny, nz=nz, tau=(0.8, 1.2), tau_d=0.9, kT=1e-4, seed=9)
+    b = fm.Lattice(fm.Params(G=0.7, rho_ref=(1.0, 1.0), **kw))
+    m = fm.Multi(fm.MultiParams(nspecies=2, G=((0.0, 0.7), (0.7, 0.0)), rho_ref=(1.0, 1.0), **kw))
+    r1, r2 = _densities(shape, 2)
+    b.init_density(r1, r2)
+    m.init_density([r1, r2])
+    b.step(50)
+    m.step(50)
+    fb, fmu = b.populations(), m.populations()
+    err = np.max(np.abs(fb - fmu)) / np.max(np.abs(fb))
+    _say("  max rel diff", err)
+    assert err <= 1e-13
+    b.close()
+    m.close()
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-13), ("f32", 2e-8)])
+def test_multi_conservation(fm, storage, tol):
+    _say("case multi conservation", storage)
+    shape = (8, 10, 12)
+    m = fm.Multi(fm.MultiParams(lattice="d3q19", storage=storage, nspecies=3, nx=12, ny=10, nz=8,
+                                tau=(0.8, 1.1, 1.3), tau_d=0.9, G=G3, kT=1e-4, rho_ref=(1.0, 0.8, 0.6), seed=2))
+    m.init_density(_densities(shape, 3))
+    s0 = m.global_sums()
+    m.step(200)
+    s1 = m.global_sums()
+    mass = s0[:3]
+    _say("  relative mass change", (s1[:3] - s0[:3]) / mass, "momentum change", s1[3:] - s0[3:])
+    assert np.all(np.abs(s1[:3] - s0[:3]) <= tol * mass)
+    assert np.all(np.abs(s1[3:] - s0[3:]) <= tol * mass.sum())
+    m.close()
+
+
+def test_multi_ideal_mixture_equipartition(fm):
+    """N = 3, G = 0, D2Q9 64 x 64, FP32, k_B T = 1e-5, tau = (0.8, 1, 1.25):
+    per-site covariances of j_bar and of the mean-subtracted densities over
+    400 snapshots 10 steps apart; diagonal within 2 %, off-diagonal within 2 %
+    of the geometric mean of the diagonal."""
+    _say("case multi equipartition")
+    L, kT = 64, 1e-5
+    rho = np.array([1.0, 0.6, 0.3])
+    m = fm.Multi(fm.MultiParams(lattice="d2q9", storage="f32", nspecies=3, nx=L, ny=L, tau=(0.8, 1.0, 1.25),
+                                tau_d=1.0, G=((0.0,) * 3,) * 3, kT=kT, rho_ref=tuple(rho), seed=31))
+    m.init_density(list(rho))
+    m.step(1000)
+    snaps = 400
+    cj = np.zeros((3, 3))
+    cr = np.zeros((3, 3))
+    for _ in range(snaps):
+        m.step(10)
+        r, j = m.moments()
+        jj = j.reshape(3, 2, -1)
+        for al in range(2):
+            cj += jj[:, al] @ jj[:, al].T / jj.shape[-1]
+        dr = r.reshape(3, -1) - r.reshape(3, -1).mean(axis=1, keepdims=True)
+        cr += dr @ dr.T / dr.shape[-1]
+    cj /= 2 * snaps
+    cr /= snaps
+    want_j = kT * np.diag(rho)
+    want_r = 3 * kT * np.diag(rho) * (1 - 1 / L ** 2)
+    for name, est, want in (("jj", cj, want_j), ("rho rho", cr, want_r)):
+        d = np.sqrt(np.diag(want))
+        rel = (est - want) / np.outer(d, d)
+        _say(f"  {name}: max |deviation| / scale = {np.max(np.abs(rel)):.4f}")
+        assert np.all(np.abs(rel) <= 0.02), (name, est, want)
+    m.close()

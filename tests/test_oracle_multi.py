@@ -145,3 +145,20 @@ def test_ideal_mixture_equipartition():
     for est, want in ((cj, want_j), (cr, want_r)):
         d = np.sqrt(np.diag(want))
         assert np.all(np.abs(est - want) <= 0.04 * np.outer(d, d)), (est, want)
+
+
+def test_four_species_d3q19_conservation():
+    """The largest normal count (D3Q19 with four species: 69 normals per site)."""
+    G = ((0.0, 0.45, 0.3, 0.2), (0.45, 0.0, 0.6, 0.1), (0.3, 0.6, 0.0, 0.5), (0.2, 0.1, 0.5, 0.0))
+    shape = (3, 4, 5)
+    m = oracle.MultiSim(oracle.MultiParams(lattice=D3Q19, nspecies=4, nx=5, ny=4, nz=3, tau=(0.8, 1.1, 1.3, 0.9),
+                                           tau_d=0.9, G=G, kT=1e-4, seed=4))
+    m.init_density([workloads.initial_density(shape, "perturbed", seed=s, amplitude=0.05)[0] for s in range(4)])
+    rho0, j0, _ = m.moments()
+    m.step(30)
+    rho1, j1, _ = m.moments()
+    f = m.populations()
+    assert np.all(np.isfinite(f))
+    mass0 = rho0.sum(axis=(1, 2, 3))
+    assert np.all(np.abs(rho1.sum(axis=(1, 2, 3)) - mass0) <= 1e-13 * mass0)
+    assert np.all(np.abs(j1.sum(axis=(0, 2, 3, 4)) - j0.sum(axis=(0, 2, 3, 4))) <= 1e-13 * mass0.sum())
