@@ -186,6 +186,102 @@ class LinearFLBE:
         return np.linalg.eigvals(M)
 
 
+class LinearMultiFLBE:
+    """The same linearisation for N species (Apps. C and D): pair couplings
+    G[N][N] (a_sigma(k) = -g(k) sum_s' G_sigma,s' delta rho_s'(k)), u =
+    (sum j + sum F / 2) / rho_t0, and the momentum noise with covariance
+    (2 lambda_d - lambda_d^2) k_B T (rho_sigma delta - rho_sigma rho_s' / rho_t)
+    per component, mapped to populations.  Uses the covariance itself, not
+    any way of sampling it."""
+
+    def __init__(self, name="d2q9", rho0=(1.0, 1.0, 1.0), tau=(1.0, 1.0, 1.0), tau_d=1.0, G=None, kT=1e-5,
+                 sdf=True):
+        self.c, self.w = lattice(name)
+        self.Q, self.D = self.c.shape
+        self.rho0 = np.array(rho0, float)
+        self.N = len(self.rho0)
+        self.lam = 1.0 / np.array(tau, float)
+        self.lam_d = 1.0 / tau_d
+        self.G = np.zeros((self.N, self.N)) if G is None else np.array(G, float)
+        self.kT = kT
+        self.sdf = sdf
+
+    def operators(self, k):
+        c, w, Q, NS = self.c, self.w, self.Q, self.N
+        k = np.asarray(k, float)
+        phase = np.exp(1j * (c @ k))
+        P = np.diag(np.conj(phase))
+        g = (w[:, None] * c * phase[:, None]).sum(0)
+        rt = self.rho0.sum()
+        n = NS * Q
+        A = np.zeros((n, n), complex)
+        for col in range(n):
+            x = np.zeros(n, complex)
+            x[col] = 1.0
+            f = [x[s * Q:(s + 1) * Q] for s in range(NS)]
+            rho = np.array([fs.sum() for fs in f])
+            j = [c.T @ fs for fs in f]
+            F = [self.rho0[s] * (-g * (self.G[s] @ rho)) for s in range(NS)]
+            u = sum(j) / rt + 0.5 * sum(F) / rt
+            out = []
+            for s in range(NS):
+                R = self.lam_d * (self.rho0[s] * u - j[s]) + (1 - 0.5 * self.lam_d) * F[s]
+                neq = f[s] - w * rho[s] - 3 * w * (c @ j[s])
+                out.append(f[s] - self.lam[s] * neq + 3 * w * (c @ R))
+            A[:, col] = np.concatenate(out)
+        PP = np.kron(np.eye(NS), P)
+        M = PP @ A
+        mu = 3.0 * self.kT
+        Xi = np.zeros((n, n))
+        Pi = np.diag(w) - np.outer(w, w) - 3 * np.outer(w, w) * (c @ c.T)
+        for s in range(NS):
+            Xi[s * Q:(s + 1) * Q, s * Q:(s + 1) * Q] = (2 * self.lam[s] - self.lam[s] ** 2) * mu * self.rho0[s] * Pi
+        if self.sdf:
+            B = 3 * w[:, None] * c
+            K = (2 * self.lam_d - self.lam_d ** 2) * self.kT * (np.diag(self.rho0) - np.outer(self.rho0, self.rho0) / rt)
+            Xi += np.kron(K, B @ B.T)
+        return M, PP @ Xi @ PP.conj().T
+
+    def covariance(self, k):
+        M, N = self.operators(k)
+        n = M.shape[0]
+        vecS = linalg.solve(np.eye(n * n) - np.kron(np.conj(M), M), N.reshape(-1, order="F"))
+        S = vecS.reshape(n, n, order="F")
+        return 0.5 * (S + S.conj().T)
+
+    def density_structure(self, k):
+        """S_rho_sigma rho_s'(k), N x N."""
+        Q = self.Q
+        E = np.kron(np.eye(self.N), np.ones((1, Q)))
+        return (E @ self.covariance(k) @ E.T).real
+
+    def momentum_structure(self, k):
+        """S_j_sigma j_s'(k) averaged over the D components, N x N."""
+        Q, c = self.Q, self.c
+        S = self.covariance(k)
+        out = np.zeros((self.N, self.N))
+        for al in range(self.D):
+            E = np.kron(np.eye(self.N), c[:, al][None, :])
+            out += (E @ S @ E.T).real
+        return out / self.D
+
+    def spectral_radius(self, k):
+        M, _ = self.operators(k)
+        return np.max(np.abs(np.linalg.eigvals(M)))
+
+
+def appendix_structure_factor(k_mag, G, rho0, kT, cs2=1.0 / 3.0):
+    """Density structure factors of the homogeneous multicomponent mixture,
+    from the self-consistency condition of App. D (mu alpha + Gamma R alpha
+    + Gamma = 0) inserted into App. C's S = mu R + R Gamma R, which gives
+    S(k) = mu (R^-1 + alpha(k))^-1, R = diag(rho0), alpha = G sin k / k
+    (lattice form along an axis, Sec. VI A); for two species this is
+    Eq. (57)."""
+    mu = kT / cs2
+    alpha = np.asarray(G, float) * np.sinc(k_mag / np.pi)
+    return mu * np.linalg.inv(np.diag(1.0 / np.asarray(rho0, float)) + alpha)
+
+
 def eq57(k_mag, G, kT, rho0=1.0, rho0p=1.0, cs2=1.0 / 3.0):
     """Eq. (57) with the lattice alpha(k) = G sin k / k for k along an axis
     (Sec. VI A): S_rho_rho and S_rho_rho'."""

@@ -8,6 +8,8 @@
 - Conservation of every species' mass and of the total momentum.
 - The ideal mixture (G = 0, N = 3) is equipartitioned at every site:
   <j_sigma j_s'> = k_B T rho_sigma delta, <drho_sigma drho_s'> = 3 k_B T rho_sigma delta.
+- Three coupled species: the six density structure factors follow the
+  lattice linear theory (whose small-k limit is App. C/D's formula).
 """
 import numpy as np
 import pytest
@@ -168,3 +170,47 @@ def test_multi_ideal_mixture_equipartition(fm):
         _say(f"  {name}: max |deviation| / scale = {np.max(np.abs(rel)):.4f}")
         assert np.all(np.abs(rel) <= 0.02), (name, est, want)
     m.close()
+
+
+def test_multi_structure_factors_against_linear_theory(fm):
+    """Three coupled, miscible species in the equilibration-ratio set-up of
+    Sec. VI A: D2Q9 64 x 2, FP64, k_B T = 1e-5, rho = (1, 0.8, 0.6), pair
+    couplings 0.4 / 0.3 / 0.5, tau = 1.  After 20000 steps, 2000 snapshots
+    50 steps apart: the six S_rho_sigma rho_s'(k) for k along x, averaged in
+    three k bands, against the lattice linear theory (tests/lyapunov.py,
+    whose small-k limit is App. C/D's mu (R^-1 + alpha)^-1), within 5
+    standard errors (at least 1 %) of the diagonal entries; the statistical
+    error of a band follows from the theory's relaxation rates as in the
+    two-species test."""
+    from lyapunov import LinearMultiFLBE
+    _say("case multi S(k) vs linear theory")
+    NX, NY, KT, EVERY, SNAPS = 64, 2, 1e-5, 50, 2000
+    rho0 = (1.0, 0.8, 0.6)
+    G = ((0.0, 0.4, 0.3), (0.4, 0.0, 0.5), (0.3, 0.5, 0.0))
+    m = fm.Multi(fm.MultiParams(lattice="d2q9", storage="f64", nspecies=3, nx=NX, ny=NY, tau=(1.0, 1.0, 1.0),
+                                tau_d=1.0, G=G, kT=KT, seed=77))
+    m.init_density(list(rho0))
+    m.step(20000)
+    acc = np.zeros((3, 3, NX))
+    for _ in range(SNAPS):
+        m.step(EVERY)
+        r = m.moments()[0][:, 0]                 # [3, NY, NX]
+        d = r - r.mean(axis=(1, 2), keepdims=True)
+        X = np.fft.fft(d.sum(axis=1), axis=1)    # k_y = 0 row
+        acc += (X[:, None, :] * np.conj(X[None, :, :])).real / (NX * NY)
+    m.close()
+    S = acc / SNAPS
+    th = LinearMultiFLBE("d2q9", rho0=rho0, tau=(1.0, 1.0, 1.0), tau_d=1.0, G=G, kT=KT)
+    ks = 2 * np.pi * np.fft.fftfreq(NX)
+    for lo, hi in ((0.15, 0.8), (0.8, 1.6), (1.6, np.pi)):
+        sel = [i for i in range(1, NX) if lo <= abs(ks[i]) < hi]
+        want = np.mean([th.density_structure([ks[i], 0.0]) for i in sel], axis=0)
+        meas = np.mean([S[:, :, i] for i in sel], axis=0)
+        kk = sorted({round(abs(ks[i]), 12) for i in sel})
+        rel = [(1 + q) / (1 - q) / SNAPS for q in (th.spectral_radius([k, 0.0]) ** (2 * EVERY) for k in kk)]
+        tol = max(0.01, 5 * float(np.sqrt(np.mean(rel) / len(kk))))
+        scale = np.sqrt(np.outer(np.diag(want), np.diag(want)))
+        dev = np.max(np.abs(meas - want) / scale)
+        _say(f"  k in [{lo:.2f},{hi:.2f}): max |S - theory| / scale = {dev:.4f} (tolerance {tol:.3f}); "
+             f"S_12 / S_11 theory {want[0, 1] / want[0, 0]:.3f}")
+        assert dev <= tol, (lo, meas, want)

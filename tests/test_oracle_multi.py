@@ -162,3 +162,43 @@ def test_four_species_d3q19_conservation():
     mass0 = rho0.sum(axis=(1, 2, 3))
     assert np.all(np.abs(rho1.sum(axis=(1, 2, 3)) - mass0) <= 1e-13 * mass0)
     assert np.all(np.abs(j1.sum(axis=(0, 2, 3, 4)) - j0.sum(axis=(0, 2, 3, 4))) <= 1e-13 * mass0.sum())
+
+
+def test_multi_linear_theory_two_species_is_the_binary_theory():
+    """The N-species linear theory with two species equals the binary one."""
+    from lyapunov import LinearFLBE, LinearMultiFLBE
+    kw = dict(rho0=(1.0, 0.7), tau=(0.8, 1.2), tau_d=0.9, kT=1e-5)
+    b = LinearFLBE("d2q9", G=0.6, **kw)
+    m = LinearMultiFLBE("d2q9", G=((0.0, 0.6), (0.6, 0.0)), **kw)
+    for k in ([0.3, 0.0], [1.1, 0.4], [2.5, 2.0]):
+        sb = b.structure_factors(k)
+        S = m.density_structure(k)
+        assert S[0, 0] == pytest.approx(sb["rho1rho1"], rel=1e-10)
+        assert S[1, 1] == pytest.approx(sb["rho2rho2"], rel=1e-10)
+        assert S[0, 1] == pytest.approx(sb["rho1rho2"], rel=1e-9, abs=1e-16)
+
+
+def test_multi_linear_theory_limits():
+    """Three species.  Ideal mixture (G = 0): S_rho rho = 3 k_B T rho_sigma
+    delta and S_jj = k_B T rho_sigma delta at every k (App. C with gamma = 0;
+    exact on the lattice).  Coupled and miscible (R^-1 + G positive
+    definite): S_rho rho(k) tends to App. C/D's mu (R^-1 + alpha)^-1 and
+    S_jj to k_B T rho delta at small k (k = 0.05 along x: within 0.05 % and
+    0.01 %; at larger k the lattice values differ from the continuum ones,
+    as for two species)."""
+    from lyapunov import LinearMultiFLBE, appendix_structure_factor
+    rho = (1.0, 0.8, 0.6)
+    kT = 1e-5
+    ideal = LinearMultiFLBE("d2q9", rho0=rho, tau=(0.9, 1.0, 1.2), tau_d=1.0, kT=kT)
+    for kk in ([0.4, 0.0], [1.3, 0.7], [2.9, 0.0]):
+        assert np.allclose(ideal.density_structure(kk), 3 * kT * np.diag(rho), rtol=1e-9, atol=1e-9 * kT)
+        assert np.allclose(ideal.momentum_structure(kk), kT * np.diag(rho), rtol=1e-9, atol=1e-9 * kT)
+    G = ((0.0, 0.4, 0.3), (0.4, 0.0, 0.5), (0.3, 0.5, 0.0))
+    th = LinearMultiFLBE("d2q9", rho0=rho, tau=(0.9, 1.0, 1.2), tau_d=1.0, G=G, kT=kT)
+    k = 0.05
+    S = th.density_structure([k, 0.0])
+    want = appendix_structure_factor(k, G, rho, kT)
+    assert np.max(np.abs(S - want)) <= 5e-4 * np.max(np.abs(want))
+    assert abs(want[0, 1]) > 0.1 * want[0, 0]  # the couplings matter at this k
+    Sj = th.momentum_structure([k, 0.0])
+    assert np.max(np.abs(Sj - kT * np.diag(rho))) <= 1e-4 * kT
