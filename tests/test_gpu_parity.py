@@ -216,10 +216,12 @@ def test_health_counts(fm):
     assert g.health() == (2, 1)
 
 
-def _sampled_full_size(fm, orc, lattice, shape, storage, phys, steps, n_samples, tol, tile=None):
+def _sampled_full_size(fm, orc, lattice, shape, storage, phys, steps, n_samples, tol, tile=None, unit_roundoff=0.0):
     """Run the full-size lattice on the GPU in the benchmark's launch shape,
     then check one more step at sampled sites against the oracle's collision
-    of the same (GPU-produced) pre-collision state."""
+    of the same (GPU-produced) pre-collision state.  For 16-bit storage the
+    bound adds the format's rounding of the largest stored deviation
+    (unit_roundoff * max |f - w rho_ref|)."""
     import workloads
     nz, ny, nx = shape
     r1, r2 = workloads.initial_density(shape, "perturbed", seed=phys["seed"], amplitude=0.01)
@@ -242,6 +244,11 @@ def _sampled_full_size(fm, orc, lattice, shape, storage, phys, steps, n_samples,
     worst = 0.0
     fmax = np.max(np.abs(f_n1))
     flat = f_n1.reshape(2, o.Q, -1)
+    if unit_roundoff:
+        ref = np.asarray(phys["rho_ref"])[:, None, None]
+        dmax = float(np.max(np.abs(flat - o.w[None, :, None] * ref)))
+        tol = tol + unit_roundoff * dmax / fmax
+        _say("largest stored deviation", dmax, "-> bound", tol)
     for s in sites:
         x, y, z = s % nx, (s // nx) % ny, s // (nx * ny)
         for i in range(o.Q):
@@ -263,6 +270,20 @@ def test_full_size_c2_sampled(fm, orc):
     _say("case full-size c2 d3q19 256^3 f32")
     _sampled_full_size(fm, orc, "d3q19", (256, 256, 256), "f32",
                        dict(tau=(1.0, 1.0), tau_d=1.0, G=1.2, kT=1e-5, seed=1), 3, 300, 2e-6)
+
+
+@pytest.mark.parametrize("storage,u", [("bf16", 2.0 ** -8), ("f16", 2.0 ** -11)])
+def test_full_size_c3_sampled(fm, orc, storage, u):
+    """C3: the C2 workload with 16-bit deviation storage, in the default
+    launch shape.  The GPU's stored step is the FP32 collision rounded to
+    the 16-bit format (round to nearest: error at most the unit roundoff u
+    of the stored deviation, u = 2^-8 for BF16, 2^-11 for FP16), so the
+    bound is 2e-6 (FP32 arithmetic, as for C2) plus u times the largest
+    deviation, relative to max |f|."""
+    _say(f"case full-size c3 d3q19 256^3 {storage}")
+    _sampled_full_size(fm, orc, "d3q19", (256, 256, 256), storage,
+                       dict(tau=(1.0, 1.0), tau_d=1.0, G=1.2, kT=1e-5, seed=1, rho_ref=(1.0, 1.0)), 3, 200, 2e-6,
+                       unit_roundoff=u)
 
 
 @pytest.mark.parametrize("lattice,shape,tiles", [
