@@ -3,9 +3,12 @@
 // transfers.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <new>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/fmlb.h"
