@@ -98,6 +98,7 @@ def lib():
         L.orc_multi_get_populations.argtypes = [ctypes.c_void_p, dp]
         L.orc_multi_step.argtypes = [ctypes.c_void_p, ctypes.c_int64]
         L.orc_multi_moments.argtypes = [ctypes.c_void_p, dp, dp, dp]
+        L.orc_multi_collide_site.argtypes = [ctypes.c_void_p, ctypes.c_int64, dp]
         _lib = L
     return _lib
 
@@ -309,6 +310,13 @@ class MultiSim:
     def step(self, n: int = 1):
         if lib().orc_multi_step(self._h, n) != 0:
             raise RuntimeError("orc_multi_step failed")
+
+    def collide_site(self, site: int) -> np.ndarray:
+        """Post-collision f*[N, Q] at one site of the stored state."""
+        out = np.zeros(self.N * self.Q)
+        if lib().orc_multi_collide_site(self._h, int(site), _dp(out)) != 0:
+            raise RuntimeError("orc_multi_collide_site failed")
+        return out.reshape(self.N, self.Q)
 
     def moments(self):
         """rho [N, *shape], j_bar [N, D, *shape], F [N, D, *shape]."""

@@ -52,6 +52,7 @@ struct orc_multi {
     double *fnew;
     double *rho;  /* [N][nsites] */
     double *j;    /* [N][3][nsites] */
+    int moments_valid; /* rho / j hold pass 1 of the current state */
 };
 
 orc_multi *orc_multi_create(const orc_multi_params *p)
@@ -132,6 +133,7 @@ int orc_multi_init_density(orc_multi *s, const double *rho)
             for (int64_t r = 0; r < s->nsites; ++r)
                 mpop(s, s->f, sp, i)[r] = s->w[i] * rho[(size_t)sp * s->nsites + r];
     s->step = 0;
+    s->moments_valid = 0;
     return 0;
 }
 
@@ -140,6 +142,7 @@ int orc_multi_set_populations(orc_multi *s, const double *f, int64_t step)
     if (!s || !f || step < 0) return -1;
     memcpy(s->f, f, (size_t)s->N * s->Q * s->nsites * sizeof(double));
     s->step = step;
+    s->moments_valid = 0;
     return 0;
 }
 
@@ -166,6 +169,7 @@ static void multi_pass1(orc_multi *s)
             s->rho[(size_t)sp * ns + r] = rho;
             for (int al = 0; al < 3; ++al) s->j[((size_t)sp * 3 + al) * ns + r] = j[al];
         }
+    s->moments_valid = 1;
 }
 
 /* a_sigma(r) = -sum_s' G_sigma,s' sum_i w_i rho_s'(r + c_i) c_i (Eq. (87)
@@ -340,7 +344,19 @@ int orc_multi_step(orc_multi *s, int64_t n)
         s->f = s->fnew;
         s->fnew = tmp;
         s->step += 1;
+        s->moments_valid = 0;
     }
+    return 0;
+}
+
+int orc_multi_collide_site(orc_multi *s, int64_t site, double *fstar)
+{
+    if (!s || !fstar || site < 0 || site >= s->nsites) return -1;
+    if (!s->moments_valid) multi_pass1(s);
+    double out[ORC_MAX_SPECIES][QMAX];
+    multi_collide_site(s, site, out);
+    for (int sp = 0; sp < s->N; ++sp)
+        for (int i = 0; i < s->Q; ++i) fstar[(size_t)sp * s->Q + i] = out[sp][i];
     return 0;
 }
 

@@ -114,6 +114,8 @@ int orc_multi_get_populations(const orc_multi *s, double *f);
 int orc_multi_step(orc_multi *s, int64_t n);
 /* rho[N][sites], j_bar[N][D][sites], F[N][D][sites] of the stored state (any may be NULL). */
 int orc_multi_moments(orc_multi *s, double *rho, double *j, double *F);
+/* Post-collision populations f*[N][Q] at one site of the stored state. */
+int orc_multi_collide_site(orc_multi *s, int64_t site, double *fstar);
 
 #ifdef __cplusplus
 }

@@ -214,3 +214,42 @@ def test_multi_structure_factors_against_linear_theory(fm):
         _say(f"  k in [{lo:.2f},{hi:.2f}): max |S - theory| / scale = {dev:.4f} (tolerance {tol:.3f}); "
              f"S_12 / S_11 theory {want[0, 1] / want[0, 0]:.3f}")
         assert dev <= tol, (lo, meas, want)
+
+
+def test_full_size_three_species_sampled(fm):
+    """The benchmark's N-species workload (D3Q19 256^3, three species, FP32,
+    pair couplings 0.5 / 0.3 / 0.4, k_B T = 1e-5): after 3 steps, one more
+    step at 150 sampled sites against the oracle's collision of the same
+    (GPU-produced) pre-collision state, within 2e-6 of max|f| (FP32
+    arithmetic, as for the two-species C2 check)."""
+    import oracle
+    import workloads
+    _say("case full-size three species d3q19 256^3 f32")
+    n, L = 3, 256
+    G = ((0.0, 0.5, 0.3), (0.5, 0.0, 0.4), (0.3, 0.4, 0.0))
+    shape = (L, L, L)
+    g = fm.Multi(fm.MultiParams(lattice="d3q19", storage="f32", nspecies=n, nx=L, ny=L, nz=L, tau=(1.0,) * n,
+                                tau_d=1.0, G=G, kT=1e-5, rho_ref=(1.0,) * n, seed=1))
+    g.init_density([workloads.initial_density(shape, "perturbed", seed=1 + s, amplitude=0.01)[0] for s in range(n)])
+    g.step(3)
+    f_n = g.populations()
+    g.step(1)
+    f_n1 = g.populations().reshape(n, 19, -1)
+    g.close()
+    o = oracle.MultiSim(oracle.MultiParams(lattice=oracle.D3Q19, nspecies=n, nx=L, ny=L, nz=L, tau=(1.0,) * n,
+                                           tau_d=1.0, G=G, kT=1e-5, seed=1))
+    o.set_populations(f_n, 3)
+    del f_n
+    rng = np.random.default_rng(0)
+    sites = rng.integers(0, L ** 3, size=150)
+    sites[:3] = [0, L ** 3 - 1, L ** 3 // 2]
+    c = o.c
+    fmax = np.max(np.abs(f_n1))
+    worst = 0.0
+    for s in sites:
+        x, y, z = s % L, (s // L) % L, s // (L * L)
+        for i in range(19):
+            src = (x - c[i, 0]) % L + L * ((y - c[i, 1]) % L + L * ((z - c[i, 2]) % L))
+            worst = max(worst, float(np.max(np.abs(f_n1[:, i, s] - o.collide_site(src)[:, i]))))
+    _say("  sampled max diff / max|f|", worst / fmax)
+    assert worst <= 2e-6 * fmax

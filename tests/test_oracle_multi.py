@@ -202,3 +202,21 @@ def test_multi_linear_theory_limits():
     assert abs(want[0, 1]) > 0.1 * want[0, 0]  # the couplings matter at this k
     Sj = th.momentum_structure([k, 0.0])
     assert np.max(np.abs(Sj - kT * np.diag(rho))) <= 1e-4 * kT
+
+
+def test_multi_collide_site_is_the_step():
+    """The single-site collision, streamed, is the next state."""
+    shape = (1, 6, 7)
+    m = oracle.MultiSim(oracle.MultiParams(nspecies=3, nx=7, ny=6, tau=(0.8, 1.1, 1.3), tau_d=0.9,
+                                           G=((0.0, 0.4, 0.3), (0.4, 0.0, 0.6), (0.3, 0.6, 0.0)), kT=1e-4, seed=3))
+    m.init_density([workloads.initial_density(shape, "perturbed", seed=s, amplitude=0.05)[0] for s in range(3)])
+    m.step(2)
+    fs = np.stack([m.collide_site(r) for r in range(m.nsites)], axis=-1)  # [N, Q, sites]
+    m.step(1)
+    f1 = m.populations().reshape(3, m.Q, -1)
+    c = m.c
+    for r in range(m.nsites):
+        x, y = r % 7, r // 7
+        for i in range(m.Q):
+            dst = (x + c[i, 0]) % 7 + 7 * ((y + c[i, 1]) % 6)
+            assert np.allclose(f1[:, i, dst], fs[:, i, r], rtol=0, atol=1e-15)
