@@ -254,6 +254,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--multi-only", action="store_true",
+                    help="time only the three-species D3Q19 256^3 FP32 workload (for profiling)")
     ap.add_argument("--traffic-json", nargs=4, metavar=("FETCH_DB", "WRITE_DB", "COPY_FETCH_DB", "COPY_WRITE_DB"))
     args = ap.parse_args()
     if args.traffic_json:
@@ -272,6 +274,11 @@ def main() -> int:
     import paper_1410_5584_amd as fm
     fm.lib()
     torch.cuda.set_device(0)
+
+    if args.multi_only:
+        print(json.dumps({"d3q19_256cube_3species_f32": multi_species(fm, torch, args.steps, args.warmup)}),
+              flush=True)
+        return 0
 
     ms, nsites, sums, health, ms_copy = time_steps(fm, torch, "f32", args.steps, args.warmup)
     ms_per_step = ms / args.steps
