@@ -277,12 +277,14 @@ fmlb_status fmlb_batch_init_density(fmlb_batch *b, int r, const double *rho1, co
 fmlb_status fmlb_batch_step(fmlb_batch *b, int64_t n, int use_graph);
 
 /* Work-list shape: tile_x sites per workgroup row (64, 128 or 256) and
- * `march` rows walked per item (1..4096); 0 = default for each.  Results do
+ * `march` rows walked per item (1..4096); 0 = default for each (the widest
+ * tile at least half the replicas fill; one row per item for batches of
+ * fewer than about 2000 tile rows, up to 16 above).  Results do
  * not depend on it.  Discards a captured graph. */
 fmlb_status fmlb_batch_set_tile(fmlb_batch *b, int tile_x, int march);
 
 /* Tile autotuner: times every supported work-list shape (tile_x 64, 128,
- * 256 x march 4, 8, 16, 32, 64) over `reps` recomputations of the next step
+ * 256 x march 1, 2, 4, 8, 16, 32, 64) over `reps` recomputations of the next step
  * (the state and the step counter are left unchanged: each trial re-reads
  * the current state and overwrites the other buffer), keeps the fastest and
  * reports it.  Synchronises.  FMLB_E_STATE until every replica is
