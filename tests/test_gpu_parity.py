@@ -272,6 +272,22 @@ def test_full_size_c2_sampled(fm, orc):
                        dict(tau=(1.0, 1.0), tau_d=1.0, G=1.2, kT=1e-5, seed=1), 3, 300, 2e-6)
 
 
+def test_lattice_beyond_32bit_offsets_runs_two_pass(fm, orc):
+    """D3Q19 384^3 FP32: one species' array is 19 x 384^3 x 4 B = 4.3 GB,
+    beyond the fused kernels' 32-bit buffer offsets, so the step runs the
+    two-pass form with 64-bit indexing; sampled sites against the oracle
+    after 2 steps, as for the 256^3 check."""
+    _say("case 384^3 d3q19 f32 (two-pass, 64-bit offsets)")
+    g = fm.Lattice(fm.Params(lattice="d3q19", storage="f32", nx=384, ny=384, nz=384))
+    with pytest.raises(fm.FmlbError) as e:
+        g.set_tile(128, 4, 0)  # fused shapes are refused at this size
+    assert e.value.status == fm.FMLB_E_INVALID
+    g.close()
+    del g
+    _sampled_full_size(fm, orc, "d3q19", (384, 384, 384), "f32",
+                       dict(tau=(1.0, 1.0), tau_d=1.0, G=0.5, kT=1e-5, seed=3), 2, 100, 2e-6)
+
+
 @pytest.mark.parametrize("storage,u", [("bf16", 2.0 ** -8), ("f16", 2.0 ** -11)])
 def test_full_size_c3_sampled(fm, orc, storage, u):
     """C3: the C2 workload with 16-bit deviation storage, in the default
