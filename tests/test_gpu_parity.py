@@ -306,6 +306,11 @@ def test_full_size_c3_sampled(fm, orc, storage, u):
     ("d3q19", (20, 19, 70), [(1, 0, 0), (64, 4, 7), (64, 8, 32), (32, 8, 3), (32, 16, 5), (128, 4, 9)]),
     ("d3q19", (7, 5, 256), [(1, 0, 0), (256, 2, 3), (256, 2, 64), (128, 4, 2), (0, 0, 0)]),
     ("d2q9", (1, 37, 300), [(1, 0, 0), (64, 1, 5), (128, 1, 16), (256, 1, 2)]),
+    # fewer planes than the three-plane ring: the plane indices wrap onto copies
+    ("d3q19", (1, 6, 70), [(1, 0, 0), (64, 4, 1), (64, 8, 3), (128, 4, 2), (0, 0, 0)]),
+    ("d3q19", (2, 5, 256), [(1, 0, 0), (256, 2, 1), (256, 2, 2), (128, 4, 5), (0, 0, 0)]),
+    ("d2q9", (1, 2, 64), [(1, 0, 0), (64, 1, 1), (64, 1, 3), (0, 0, 0)]),
+    ("d2q9", (1, 1, 300), [(1, 0, 0), (256, 1, 1), (128, 1, 4), (0, 0, 0)]),
 ])
 @pytest.mark.parametrize("storage", ["f32", "bf16", "f16"])
 def test_launch_shape_invariance_bitwise(fm, lattice, shape, tiles, storage):
