@@ -115,6 +115,7 @@ _SIGNATURES = {
     "fmlb_multi_init_density": (ctypes.c_int32, [_vp, _dp]),
     "fmlb_multi_step": (ctypes.c_int32, [_vp, ctypes.c_int64]),
     "fmlb_multi_current_step": (ctypes.c_int64, [_vp]),
+    "fmlb_multi_set_tile": (ctypes.c_int32, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "fmlb_multi_get_populations": (ctypes.c_int32, [_vp, _dp, ctypes.c_size_t]),
     "fmlb_multi_set_populations": (ctypes.c_int32, [_vp, _dp, ctypes.c_size_t, ctypes.c_int64]),
     "fmlb_multi_moments": (ctypes.c_int32, [_vp, _dp, _dp]),
@@ -363,6 +364,10 @@ def fmlb_multi_step(m: int, n: int):
 
 def fmlb_multi_current_step(m: int) -> int:
     return lib().fmlb_multi_current_step(_vp(m))
+
+
+def fmlb_multi_set_tile(m: int, tile_x: int, tile_y: int, march: int):
+    _check("fmlb_multi_set_tile", lib().fmlb_multi_set_tile(_vp(m), tile_x, tile_y, march))
 
 
 def fmlb_multi_get_populations(m: int, out: np.ndarray):
@@ -668,6 +673,10 @@ class Multi:
 
     def step(self, n: int = 1):
         fmlb_multi_step(self.m, n)
+
+    def set_tile(self, tile_x: int = 0, tile_y: int = 0, march: int = 0):
+        """tile_x 0 (default) or 1: the two-pass form; otherwise a fused tile."""
+        fmlb_multi_set_tile(self.m, tile_x, tile_y, march)
 
     def populations(self):
         out = np.empty((self.N, self.Q) + self.shape)

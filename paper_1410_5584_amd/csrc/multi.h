@@ -27,6 +27,15 @@ namespace fmlb {
 
 constexpr int kMaxSpecies = 4;
 
+// Velocity components along plane axis 0 (x), plane axis 1 (y, 3D only) and
+// the march axis (z in 3D, y in 2D).
+template <class L>
+struct MarchAxesN {
+    static constexpr int c0(int i) { return L::cx[i]; }
+    static constexpr int c1(int i) { return L::D == 3 ? L::cy[i] : 0; }
+    static constexpr int cm(int i) { return L::D == 3 ? L::cz[i] : L::cy[i]; }
+};
+
 template <class Real>
 struct MultiPhys {
     Real lam[kMaxSpecies];   // 1 / tau_sigma
@@ -72,22 +81,12 @@ __global__ __launch_bounds__(256) void multi_potential_kernel(MultiArgs<S> a)
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y, z = blockIdx.z;
     if (x >= a.g.nx) return;
-    Real f[N][L::Q];
+    Real f[N][L::Q], phi[N];
     multi_pull<L, S, N>(a.src, a.g, x, y, z, f);
-    Real dr[N];
-#pragma unroll
-    for (int s = 0; s < N; ++s) {
-        Real j[3];
-        moments<L, Real>(f[s], dr[s], j);
-    }
+    multi_potential<L, S, N>(a.ph, f, phi);
     const size_t site = (size_t)x + (size_t)a.g.nx * ((size_t)y + (size_t)a.g.ny * (size_t)z);
 #pragma unroll
-    for (int s = 0; s < N; ++s) {
-        Real v = 0;
-#pragma unroll
-        for (int t = 0; t < N; ++t) v += a.ph.G[s][t] * dr[t];
-        a.phi[(size_t)s * a.g.nsites + site] = v;
-    }
+    for (int s = 0; s < N; ++s) a.phi[(size_t)s * a.g.nsites + site] = phi[s];
 }
 
 // Momentum noise xi[N][3] of one site from the normals z[0 .. D(N-1)-1].
@@ -141,41 +140,17 @@ __device__ __forceinline__ void multi_momentum_noise(const Real (&rho)[N], Real 
     }
 }
 
+// Moments, velocities, noise and collision of one site, then the stores:
+// everything of the step after the pull and the force (shared by the
+// two-pass and the fused kernels, so both give the same bits).
 template <class L, class S, int N>
-__global__ __launch_bounds__(256) void multi_step_kernel(MultiArgs<S> a)
+__device__ __forceinline__ void multi_collide_store(const MultiArgs<S> &a, typename Storage<S>::Real (&f)[N][L::Q],
+                                                    typename Storage<S>::Real (&acc)[N][3], size_t site)
 {
     using Real = typename Storage<S>::Real;
     constexpr int Q = L::Q, D = L::D, NS = Q - D - 1;
     constexpr int K = D * (N - 1) + N * NS;
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int y = blockIdx.y, z = blockIdx.z;
-    if (x >= a.g.nx) return;
-    const Geom g = a.g;
     const MultiPhys<Real> &ph = a.ph;
-    Real f[N][Q];
-    multi_pull<L, S, N>(a.src, g, x, y, z, f);
-
-    // force from the neighbours' potentials: a_sigma = -sum_i w_i c_i phi_sigma(r + c_i)
-    Real acc[N][3];
-#pragma unroll
-    for (int s = 0; s < N; ++s) {
-        Real ax = 0, ay = 0, az = 0;
-#pragma unroll
-        for (int i = 1; i < Q; ++i) {
-            const int xn = wrap(x, L::cx[i], g.nx);
-            const int yn = wrap(y, L::cy[i], g.ny);
-            const int zn = D == 3 ? wrap(z, L::cz[i], g.nz) : 0;
-            const Real t = Real(L::w36[i]) / Real(36) *
-                           a.phi[(size_t)s * g.nsites + (size_t)xn + (size_t)g.nx * ((size_t)yn + (size_t)g.ny * zn)];
-            if (L::cx[i]) ax += L::cx[i] > 0 ? t : -t;
-            if (L::cy[i]) ay += L::cy[i] > 0 ? t : -t;
-            if (D == 3 && L::cz[i]) az += L::cz[i] > 0 ? t : -t;
-        }
-        acc[s][0] = -ax;
-        acc[s][1] = -ay;
-        acc[s][2] = -az;
-    }
-
     Real dr[N], rho[N], j[N][3], F[N][3];
     Real rt = 0;
 #pragma unroll
@@ -202,7 +177,6 @@ __global__ __launch_bounds__(256) void multi_step_kernel(MultiArgs<S> a)
     }
 
     // every normal of the site, in stream order (word w: normals 2w, 2w + 1)
-    const size_t site = (size_t)x + (size_t)g.nx * ((size_t)y + (size_t)g.ny * (size_t)z);
     const Counter ctr{(uint32_t)site, a.step_lo, a.step_hi};
     Real znorm[K + 1];
 #pragma unroll
@@ -223,7 +197,176 @@ __global__ __launch_bounds__(256) void multi_step_kernel(MultiArgs<S> a)
         relax_species<L, Real>(f[s], rho[s], dr[s], j[s], acc[s], F[s], u, ph.lam[s], ph.lam_d, ph.gain[s], Real(1),
                                xi[s], znorm + D * (N - 1) + s * NS);
 #pragma unroll
-        for (int i = 0; i < Q; ++i) Storage<S>::store(a.dst, ((size_t)(s * Q + i)) * g.nsites + site, f[s][i]);
+        for (int i = 0; i < Q; ++i) Storage<S>::store(a.dst, ((size_t)(s * Q + i)) * a.g.nsites + site, f[s][i]);
+    }
+}
+
+// a_sigma = -sum_i w_i c_i phi_sigma(r + c_i), phi read through nb(i, sigma).
+template <class L, class Real, int N, class NB>
+__device__ __forceinline__ void multi_force(const NB &nb, Real (&acc)[N][3])
+{
+#pragma unroll
+    for (int s = 0; s < N; ++s) {
+        Real ax = 0, ay = 0, az = 0;
+#pragma unroll
+        for (int i = 1; i < L::Q; ++i) {
+            const Real t = Real(L::w36[i]) / Real(36) * nb(i, s);
+            if (L::cx[i]) ax += L::cx[i] > 0 ? t : -t;
+            if (L::cy[i]) ay += L::cy[i] > 0 ? t : -t;
+            if (L::D == 3 && L::cz[i]) az += L::cz[i] > 0 ? t : -t;
+        }
+        acc[s][0] = -ax;
+        acc[s][1] = -ay;
+        acc[s][2] = -az;
+    }
+}
+
+// phi_sigma = sum_s' G_sigma,s' drho_s' from the pulled populations.
+template <class L, class S, int N>
+__device__ __forceinline__ void multi_potential(const MultiPhys<typename Storage<S>::Real> &ph,
+                                                const typename Storage<S>::Real (&f)[N][L::Q],
+                                                typename Storage<S>::Real (&phi)[N])
+{
+    using Real = typename Storage<S>::Real;
+    Real dr[N];
+#pragma unroll
+    for (int s = 0; s < N; ++s) {
+        Real j[3];
+        moments<L, Real>(f[s], dr[s], j);
+    }
+#pragma unroll
+    for (int s = 0; s < N; ++s) {
+        Real v = 0;
+#pragma unroll
+        for (int t = 0; t < N; ++t) v += ph.G[s][t] * dr[t];
+        phi[s] = v;
+    }
+}
+
+template <class L, class S, int N>
+__global__ __launch_bounds__(256) void multi_step_kernel(MultiArgs<S> a)
+{
+    using Real = typename Storage<S>::Real;
+    constexpr int Q = L::Q, D = L::D;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y, z = blockIdx.z;
+    if (x >= a.g.nx) return;
+    const Geom g = a.g;
+    Real f[N][Q];
+    multi_pull<L, S, N>(a.src, g, x, y, z, f);
+    Real acc[N][3];
+    multi_force<L, Real, N>(
+        [&](int i, int s) -> Real {
+            const int xn = wrap(x, L::cx[i], g.nx);
+            const int yn = wrap(y, L::cy[i], g.ny);
+            const int zn = D == 3 ? wrap(z, L::cz[i], g.nz) : 0;
+            return a.phi[(size_t)s * g.nsites + (size_t)xn + (size_t)g.nx * ((size_t)yn + (size_t)g.ny * zn)];
+        },
+        acc);
+    const size_t site = (size_t)x + (size_t)g.nx * ((size_t)y + (size_t)g.ny * (size_t)z);
+    multi_collide_store<L, S, N>(a, f, acc, site);
+}
+
+// Single-pass form.  A workgroup owns a T0 x T1 tile of the plane
+// orthogonal to the march axis (z in 3D, y in 2D) and walks `chunk` planes.
+// For plane m+1 every tile and halo-ring site pulls its populations and
+// writes its potentials into a four-plane LDS ring; after one barrier the
+// force of plane m comes from the ring, and the tile re-pulls plane m
+// (read one plane earlier, so from cache rather than HBM) to collide and
+// store it.  Against the two-pass form this saves the HBM read of the whole
+// state per step and the potentials' round trip; the arithmetic is the same
+// (same helpers, same order), so the results are bit-identical.
+template <class L, class S, int N, int T0, int T1>
+__global__ __launch_bounds__(T0 *T1) void multi_fused_kernel(MultiArgs<S> a, int chunk)
+{
+    using Real = typename Storage<S>::Real;
+    using A = MarchAxesN<L>;
+    constexpr int Q = L::Q;
+    constexpr bool D3 = L::D == 3;
+    constexpr int H0 = T0 + 2, H1 = D3 ? T1 + 2 : 1, OFF1 = D3 ? 1 : 0;
+    constexpr int PLANE = H0 * H1, NT = T0 * T1, NHALO = PLANE - NT;
+    static_assert(D3 || T1 == 1, "2D tiles are one row");
+    static_assert(NHALO <= NT, "halo ring larger than the tile");
+    __shared__ Real ring[4][N][PLANE];
+
+    const Geom g = a.g;
+    const int n0 = g.nx, n1 = D3 ? g.ny : 1, nm = D3 ? g.nz : g.ny;
+    const int tiles0 = (n0 + T0 - 1) / T0, tiles1 = (n1 + T1 - 1) / T1;
+    const int t0 = (int)(blockIdx.x % (unsigned)tiles0);
+    const int t1 = (int)((blockIdx.x / (unsigned)tiles0) % (unsigned)tiles1);
+    const int ck = (int)(blockIdx.x / ((unsigned)tiles0 * tiles1));
+    const int mbeg = ck * chunk, mend = min(mbeg + chunk, nm);
+
+    const int tid = threadIdx.x;
+    const int l0 = tid % T0, l1 = tid / T0;
+    const int p0raw = t0 * T0 + l0, p1raw = t1 * T1 + l1;
+    const bool inside = p0raw < n0 && p1raw < n1;
+    const int p0 = p0raw % n0, p1 = p1raw % n1;
+    const int box_own = (l1 + OFF1) * H0 + (l0 + 1);
+    // halo ring: the rows / columns around the tile, one site per thread
+    int hb = -1, hp0 = 0, hp1 = 0;
+    if (tid < NHALO) {
+        int h0, h1;
+        if (!D3) {
+            h0 = tid == 0 ? 0 : H0 - 1;
+            h1 = 0;
+        } else if (tid < H0) {
+            h0 = tid;
+            h1 = 0;
+        } else if (tid < 2 * H0) {
+            h0 = tid - H0;
+            h1 = H1 - 1;
+        } else {
+            const int q = tid - 2 * H0;
+            h0 = (q & 1) ? H0 - 1 : 0;
+            h1 = 1 + (q >> 1);
+        }
+        hb = h1 * H0 + h0;
+        hp0 = ((t0 * T0 - 1 + h0) % n0 + n0) % n0;
+        hp1 = D3 ? ((t1 * T1 - OFF1 + h1) % n1 + n1) % n1 : 0;
+    }
+    auto slot = [&](int m) { return (m - mbeg + 1) & 3; };
+    auto wrapm = [&](int m) { return m < 0 ? m + nm : (m >= nm ? m - nm : m); };
+    // plane coordinates (q0, q1, m) -> lattice (x, y, z)
+    auto pull_at = [&](int q0, int q1, int m, Real (&f)[N][Q]) {
+        if constexpr (D3)
+            multi_pull<L, S, N>(a.src, g, q0, q1, m, f);
+        else
+            multi_pull<L, S, N>(a.src, g, q0, m, 0, f);
+    };
+    auto put_potentials = [&](int m) {
+        Real f[N][Q], phi[N];
+        pull_at(p0, p1, wrapm(m), f);
+        multi_potential<L, S, N>(a.ph, f, phi);
+#pragma unroll
+        for (int s = 0; s < N; ++s) ring[slot(m)][s][box_own] = phi[s];
+        if (hb >= 0) {
+            pull_at(hp0, hp1, wrapm(m), f);
+            multi_potential<L, S, N>(a.ph, f, phi);
+#pragma unroll
+            for (int s = 0; s < N; ++s) ring[slot(m)][s][hb] = phi[s];
+        }
+    };
+
+    put_potentials(mbeg - 1);
+    put_potentials(mbeg);
+#pragma unroll 1
+    for (int m = mbeg; m < mend; ++m) {
+        put_potentials(m + 1);
+        __syncthreads();
+        Real acc[N][3];
+        multi_force<L, Real, N>(
+            [&](int i, int s) -> Real {
+                return ring[slot(m + A::cm(i))][s][box_own + A::c1(i) * H0 + A::c0(i)];
+            },
+            acc);
+        if (inside) {
+            Real f[N][Q];
+            pull_at(p0, p1, m, f);
+            const size_t site = D3 ? (size_t)p0 + (size_t)n0 * ((size_t)p1 + (size_t)n1 * (size_t)m)
+                                   : (size_t)p0 + (size_t)n0 * (size_t)m;
+            multi_collide_store<L, S, N>(a, f, acc, site);
+        }
     }
 }
 

@@ -88,6 +88,7 @@ struct fmlb_multi {
     int cur;
     int64_t step;
     bool ready;
+    int tile_x, tile_y, march;  // 0: defaults; tile_x 1: two-pass form
 };
 
 namespace {
@@ -137,11 +138,74 @@ MultiPhys<Real> multi_phys(const fmlb_multi_params &p)
 
 double ref_of(const fmlb_multi *m, int s) { return m->p.storage == FMLB_F64 ? 0.0 : m->p.rho_ref[s]; }
 
+// Fused tiles: D3Q19 64x4, 64x8, 32x8; D2Q9 64x1, 128x1, 256x1.
+bool multi_tile_valid(int D, int tx, int ty)
+{
+    if (D == 3) return (tx == 64 && (ty == 4 || ty == 8)) || (tx == 32 && ty == 8);
+    return ty == 1 && (tx == 64 || tx == 128 || tx == 256);
+}
+
+// Default march of a fused tile: the longest that still gives about two
+// workgroups per CU.
+void multi_default_tile(const fmlb_multi *m, int &tx, int &ty, int &march)
+{
+    const Geom &g = m->g;
+    if (m->tile_x > 1) {
+        tx = m->tile_x;
+        ty = m->tile_y;
+    } else if (m->D == 3) {
+        tx = 64;
+        ty = 8;
+    } else {
+        tx = g.nx >= 256 ? 256 : (g.nx >= 128 ? 128 : 64);
+        ty = 1;
+    }
+    const long cols = (long)((g.nx + tx - 1) / tx) * (m->D == 3 ? (long)((g.ny + ty - 1) / ty) : 1L);
+    const int nm = m->D == 3 ? g.nz : g.ny;
+    march = 1;
+    while (march < 64 && cols * ((nm + 2L * march - 1) / (2L * march)) >= 512) march *= 2;
+}
+
+template <class L, class S, int N, int T0, int T1>
+hipError_t multi_fused_launch(const MultiArgs<S> &a, int march, hipStream_t stream)
+{
+    const Geom &g = a.g;
+    const int n1 = L::D == 3 ? g.ny : 1, nm = L::D == 3 ? g.nz : g.ny;
+    const unsigned blocks = (unsigned)((g.nx + T0 - 1) / T0) * (unsigned)((n1 + T1 - 1) / T1) *
+                            (unsigned)((nm + march - 1) / march);
+    hipLaunchKernelGGL((multi_fused_kernel<L, S, N, T0, T1>), dim3(blocks), dim3(T0 * T1), 0, stream, a, march);
+    return hipGetLastError();
+}
+
+template <class L, class S, int N>
+hipError_t multi_fused_dispatch(const MultiArgs<S> &a, int tx, int ty, int march, hipStream_t stream)
+{
+    if constexpr (L::D == 3) {
+        if (tx == 64 && ty == 4) return multi_fused_launch<L, S, N, 64, 4>(a, march, stream);
+        if (tx == 64 && ty == 8) return multi_fused_launch<L, S, N, 64, 8>(a, march, stream);
+        return multi_fused_launch<L, S, N, 32, 8>(a, march, stream);
+    } else {
+        if (tx == 64) return multi_fused_launch<L, S, N, 64, 1>(a, march, stream);
+        if (tx == 128) return multi_fused_launch<L, S, N, 128, 1>(a, march, stream);
+        return multi_fused_launch<L, S, N, 256, 1>(a, march, stream);
+    }
+}
+
 template <class L, class S, int N>
 fmlb_status multi_run(fmlb_multi *m, int64_t n)
 {
     using Real = typename Storage<S>::Real;
     const Grid gr = multi_grid(m->g);
+    // Default: the two-pass form (measured faster at 256^3, three species:
+    // 2.37 ms against 2.72 ms for the best fused tile); the fused form runs
+    // when a fused tile is set.
+    int tx = m->tile_x, ty = m->tile_y, march = m->march;
+    const bool fused = tx > 1;
+    if (fused && march == 0) {
+        int dtx, dty, dm;
+        multi_default_tile(m, dtx, dty, dm);
+        march = dm;
+    }
     for (int64_t t = 0; t < n; ++t) {
         MultiArgs<S> a{};
         a.src = reinterpret_cast<const S *>(m->pops[m->cur]);
@@ -151,10 +215,14 @@ fmlb_status multi_run(fmlb_multi *m, int64_t n)
         a.ph = multi_phys<Real>(m->p);
         a.step_lo = (uint32_t)(uint64_t)m->step;
         a.step_hi = (uint32_t)((uint64_t)m->step >> 32);
-        hipLaunchKernelGGL((multi_potential_kernel<L, S, N>), gr.grid, gr.block, 0, m->stream, a);
-        MULTI_TRY(hipGetLastError());
-        hipLaunchKernelGGL((multi_step_kernel<L, S, N>), gr.grid, gr.block, 0, m->stream, a);
-        MULTI_TRY(hipGetLastError());
+        if (fused) {
+            MULTI_TRY(multi_fused_dispatch<L, S, N>(a, tx, ty, march, m->stream));
+        } else {
+            hipLaunchKernelGGL((multi_potential_kernel<L, S, N>), gr.grid, gr.block, 0, m->stream, a);
+            MULTI_TRY(hipGetLastError());
+            hipLaunchKernelGGL((multi_step_kernel<L, S, N>), gr.grid, gr.block, 0, m->stream, a);
+            MULTI_TRY(hipGetLastError());
+        }
         m->cur = 1 - m->cur;
         m->step += 1;
     }
@@ -206,6 +274,18 @@ fmlb_status fmlb_multi_create(const fmlb_multi_params *p, void *hip_stream, void
 void fmlb_multi_destroy(fmlb_multi *m) { delete m; }
 
 int64_t fmlb_multi_current_step(const fmlb_multi *m) { return m ? m->step : -1; }
+
+fmlb_status fmlb_multi_set_tile(fmlb_multi *m, int tile_x, int tile_y, int march)
+{
+    if (!m) return FMLB_E_NULL;
+    if (tile_x < 0 || tile_y < 0 || march < 0 || march > 4096) return FMLB_E_INVALID;
+    if (tile_x > 1 && !multi_tile_valid(m->D, tile_x, tile_y)) return FMLB_E_INVALID;
+    if (tile_x <= 1 && tile_y != 0) return FMLB_E_INVALID;
+    m->tile_x = tile_x;
+    m->tile_y = tile_y;
+    m->march = march;
+    return FMLB_OK;
+}
 
 fmlb_status fmlb_multi_init_density(fmlb_multi *m, const double *rho)
 {
