@@ -860,8 +860,8 @@ void default_fused_shape(const Geom &g, int &tx, int &ty, int &chunk)
 {
     if (L::D == 3) {
         // Tiles measured on 256^3 (FP32: full-width 256x2 rows, else 128x4;
-        // 16-bit: 64x8) and from 16^3 to 128^3 (narrower tiles for narrower
-        // lattices).  The march is then the longest that still gives one
+        // 16-bit: 64x4, 1 % ahead of 64x8) and from 16^3 to 128^3 (narrower
+        // tiles for narrower lattices).  The march is then the longest that still gives one
         // workgroup per CU (256): fewer workgroups leave CUs idle, while more,
         // shorter marches re-read more halo planes (128^3 FP32: 149 us at 256
         // workgroups, 160 us at 512, 252 us at 128).
@@ -873,7 +873,7 @@ void default_fused_shape(const Geom &g, int &tx, int &ty, int &chunk)
             ty = 4;
         } else if (g.nx >= 64) {
             tx = 64;
-            ty = sizeof(S) == 4 ? 4 : 8;
+            ty = 4;
         } else {
             tx = 32;
             ty = 8;
