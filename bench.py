@@ -246,6 +246,17 @@ def cpu_baseline(steps: int = 5):
             "sample": f"{steps} steps of the full 256^3 D3Q19 workload in FP64 ({dt:.1f} s)"}
 
 
+def storage16(fm, torch, storage, steps, warmup, mlups_f32=None) -> dict:
+    """The headline workload with BF16 or FP16 deviation storage."""
+    ms16, nsites, _, _, _ = time_steps(fm, torch, storage, steps, warmup)
+    m16 = nsites * steps / (ms16 / 1e3) / 1e6
+    rec = {"value": round(m16, 2), "unit": "MLUPS", "ms_per_step": round(ms16 / steps, 4)}
+    if mlups_f32:
+        rec["vs_f32"] = round(m16 / mlups_f32, 3)
+    rec["hbm_frac"] = round(BYTES_PER_SITE[("d3q19", storage)] * nsites / (ms16 / steps / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+    return rec
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -256,6 +267,8 @@ def main() -> int:
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--multi-only", action="store_true",
                     help="time only the three-species D3Q19 256^3 FP32 workload (for profiling)")
+    ap.add_argument("--storage-only", choices=("bf16", "f16"),
+                    help="time only the D3Q19 256^3 workload with this 16-bit storage (for profiling)")
     ap.add_argument("--traffic-json", nargs=4, metavar=("FETCH_DB", "WRITE_DB", "COPY_FETCH_DB", "COPY_WRITE_DB"))
     args = ap.parse_args()
     if args.traffic_json:
@@ -275,6 +288,10 @@ def main() -> int:
     fm.lib()
     torch.cuda.set_device(0)
 
+    if args.storage_only:
+        print(json.dumps({f"d3q19_256cube_{args.storage_only}_dev":
+                          storage16(fm, torch, args.storage_only, args.steps, args.warmup)}), flush=True)
+        return 0
     if args.multi_only:
         print(json.dumps({"d3q19_256cube_3species_f32": multi_species(fm, torch, args.steps, args.warmup)}),
               flush=True)
@@ -306,13 +323,7 @@ def main() -> int:
     if not args.no_variants:
         var = {}
         for storage in ("bf16", "f16"):
-            ms16, _, _, h16, _ = time_steps(fm, torch, storage, args.steps, args.warmup)
-            m16 = nsites * args.steps / (ms16 / 1e3) / 1e6
-            var[f"d3q19_256cube_{storage}_dev"] = {
-                "value": round(m16, 2), "unit": "MLUPS", "ms_per_step": round(ms16 / args.steps, 4),
-                "vs_f32": round(m16 / mlups, 3),
-                "hbm_frac": round(BYTES_PER_SITE[("d3q19", storage)] * nsites / (ms16 / args.steps / 1e3) / 1e9
-                                  / HBM_PEAK_GBS, 4)}
+            var[f"d3q19_256cube_{storage}_dev"] = storage16(fm, torch, storage, args.steps, args.warmup, mlups)
         ms1, n1, _, _, _ = time_steps(fm, torch, "f32", args.steps, args.warmup, work=C1)
         var["d2q9_1024sq_f32"] = {"value": round(n1 * args.steps / (ms1 / 1e3) / 1e6, 2), "unit": "MLUPS",
                                   "ms_per_step": round(ms1 / args.steps, 4),

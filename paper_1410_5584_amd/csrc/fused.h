@@ -702,9 +702,19 @@ __device__ __forceinline__ void fused_tile_rows(const StepArgs<L, S> &a, int t0,
                                                          0, 0);
         }
     };
-    auto pull1 = [&](int s, int q0, int q1, int m, Real (&f)[2][Q]) {
+    // Register pull of one species.  16-bit words stay raw until they are
+    // read: a widening next to its load, between the scheduling fences
+    // below, would make every load wait for all memory operations in flight
+    // (256x2 BF16: 1.89 -> 0.99 ms per step at 256^3).
+    using HaloWord = std::conditional_t<ES == 4, Real, Raw>;
+    auto pull1 = [&](int s, int q0, int q1, int m, HaloWord (&w)[2][Q]) {
 #pragma unroll
-        for (int i = 0; i < Q; ++i) f[s][i] = BufIO<S>::load(rsrc[s], pull_off(q0, q1, m, i), (uint32_t)i * pop_bytes);
+        for (int i = 0; i < Q; ++i) {
+            if constexpr (ES == 4)
+                w[s][i] = BufIO<S>::load(rsrc[s], pull_off(q0, q1, m, i), (uint32_t)i * pop_bytes);
+            else
+                w[s][i] = __builtin_amdgcn_raw_buffer_load_b16(rsrc[s], pull_off(q0, q1, m, i), (uint32_t)i * pop_bytes, 0);
+        }
     };
 
     // Issue schedule of one plane (per thread: 38 row loads into LDS, 38
@@ -749,8 +759,13 @@ __device__ __forceinline__ void fused_tile_rows(const StepArgs<L, S> &a, int t0,
         }
     }
     dma_pull(p0, p1, wrapm(mbeg + 1), &own[0][0], NT);
-    Real hn[2][Q];
-    pull(hp0, hp1, wrapm(mbeg + 1), hn);
+    HaloWord hn[2][Q];
+    if constexpr (ES == 4) {
+        pull(hp0, hp1, wrapm(mbeg + 1), hn);
+    } else {
+        pull1(0, hp0, hp1, wrapm(mbeg + 1), hn);
+        pull1(1, hp0, hp1, wrapm(mbeg + 1), hn);
+    }
 
 #pragma unroll 1
     for (int m = mbeg; m < mend; ++m) {
@@ -766,7 +781,14 @@ __device__ __forceinline__ void fused_tile_rows(const StepArgs<L, S> &a, int t0,
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
             Real r, j[3];
-            moments<L, Real>(hn[s], r, j);
+            if constexpr (ES == 4) {
+                moments<L, Real>(hn[s], r, j);
+            } else {
+                Real h[Q];
+#pragma unroll
+                for (int i = 0; i < Q; ++i) h[i] = DmaWord<S>::decode(hn[s][i]);
+                moments<L, Real>(h, r, j);
+            }
             put_ring(ring[slot(m + 1)][s], hb, hx, r);
         }
         if (m + 2 <= mend) pull1(0, hp0, hp1, wrapm(m + 2), hn);
