@@ -91,6 +91,42 @@ def test_batch_against_oracle(fm, orc):
     b.close()
 
 
+def test_full_size_c4_sampled(fm, orc):
+    """The benchmark's batched workload at full size: 512 replicas (sizes
+    32^2..256^2, per-replica seed, k_BT and G), work list autotuned, steps
+    from one replayed 32-step HIP graph, as the benchmark times them.  Five
+    replicas (the smallest, the largest and three drawn with a fixed seed)
+    are stepped alone by the FP64 oracle and compared site by site, to the
+    FP32 bound of the single-lattice parity tests (2e-5 relative)."""
+    import workloads
+    reps = workloads.replica_table(512)
+    ps = [fm.Params(lattice="d2q9", storage="f32", nx=r["L"], ny=r["L"], nz=1, tau=r["tau"], tau_d=r["tau_d"],
+                    G=r["G"], kT=r["kT"], seed=r["seed"]) for r in reps]
+    sizes = [p.nx for p in ps]
+    picks = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)),
+                    *np.random.default_rng(7).choice(len(ps), 3, replace=False).tolist()})
+    _say("case c4 full size, 512 replicas, sampled", picks, [sizes[r] for r in picks])
+    b = fm.Batch(ps)
+    for r in range(len(ps)):
+        b.init_density(r, 1.0, 1.0)
+    tile = b.autotune(reps=2)
+    _say("autotuned tile", tile)
+    b.step(32, use_graph=True)
+    assert b.step_count == 32
+    for r in picks:
+        p = ps[r]
+        o = orc.Sim(orc.Params(lattice=0, nx=p.nx, ny=p.ny, nz=1, tau=p.tau, tau_d=p.tau_d, G=p.G, kT=p.kT,
+                               seed=p.seed))
+        o.init_density(1.0, 1.0)
+        o.step(32)
+        want = o.populations()
+        got = b.populations(r)
+        err = float(np.max(np.abs(got - want)) / np.max(np.abs(want)))
+        _say("replica", r, "L", p.nx, "G", round(p.G, 3), "kT", p.kT, "max rel diff", err)
+        assert err <= 2e-5, (r, err)
+    b.close()
+
+
 @pytest.mark.parametrize("tile,march", [(64, 1), (128, 5), (256, 16), (64, 200)])
 def test_batch_work_list_shape_invariance(fm, tile, march):
     _say("case batch tile", tile, march)
