@@ -901,13 +901,16 @@ template <class L, class S>
 void default_fused_shape(const Geom &g, int &tx, int &ty, int &chunk)
 {
     if (L::D == 3) {
-        // Tiles measured on 256^3 (FP32: full-width 256x2 rows, else 128x4;
-        // 16-bit: 64x4, 1 % ahead of 64x8) and from 16^3 to 128^3 (narrower
-        // tiles for narrower lattices).  The march is then the longest that still gives one
-        // workgroup per CU (256): fewer workgroups leave CUs idle, while more,
-        // shorter marches re-read more halo planes (128^3 FP32: 149 us at 256
-        // workgroups, 160 us at 512, 252 us at 128).
-        if (sizeof(S) == 4 && g.nx == 256) {
+        // Tiles measured on 256^3 (full-width 256x2 rows for every storage:
+        // FP32 1.02 ms against 1.17 for 128x4, BF16 0.89 against 0.95 for
+        // 64x4; other widths: FP32 128x4, 16-bit 64x4) and from 16^3 to 128^3
+        // (narrower tiles for narrower lattices).  The march is then the
+        // longest that still gives one workgroup per CU (256): fewer
+        // workgroups leave CUs idle, while more, shorter marches re-read more
+        // halo planes (128^3 FP32: 149 us at 256 workgroups, 160 us at 512,
+        // 252 us at 128; 256^3 BF16 full-width rows: 0.886 ms at 128 planes,
+        // 0.900 at 64, 0.915 at 32).
+        if (g.nx == 256) {
             tx = 256;
             ty = 2;
         } else if (sizeof(S) == 4 && g.nx >= 128) {
