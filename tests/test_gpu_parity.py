@@ -203,6 +203,38 @@ def test_observables_match_oracle(fm, orc):
     assert np.allclose(ratios, ref, rtol=1e-9)
 
 
+def test_zero_and_negative_step_counts(fm):
+    """step(0) is a no-op and step(-1) is rejected with FMLB_E_INVALID before
+    any launch, on a lattice, a batch and an N-species lattice alike: the
+    state and the step counter are unchanged bit for bit."""
+    _say("case step counts 0 and -1")
+    lat = fm.Lattice(fm.Params(lattice="d3q19", storage="f32", nx=16, ny=8, nz=6, tau=(0.9, 1.1), tau_d=1.0,
+                               G=0.5, kT=1e-4, seed=3))
+    lat.init_density(1.0, 0.9)
+    lat.step(3)
+    b = fm.Batch([fm.Params(lattice="d2q9", storage="f32", nx=20, ny=12, nz=1, tau=(1.0, 1.0), tau_d=1.0,
+                            G=0.3, kT=1e-5, seed=4)])
+    b.init_density(0, 1.0, 1.0)
+    b.step(3)
+    m = fm.Multi(fm.MultiParams(lattice="d2q9", storage="f32", nspecies=3, nx=10, ny=9, nz=1,
+                                tau=(1.0, 0.9, 1.2), tau_d=1.0, G=((0, 0.4, 0.3), (0.4, 0, 0.5), (0.3, 0.5, 0)),
+                                kT=1e-5, rho_ref=(1.0, 0.8, 0.6), seed=5))
+    m.init_density([1.0, 0.8, 0.6])
+    m.step(3)
+    before = (lat.save_raw()[0].copy(), b.populations(0), m.populations())
+    for obj in (lat, b, m):
+        obj.step(0)
+        with pytest.raises(fm.FmlbError) as e:
+            obj.step(-1)
+        assert e.value.status == fm.FMLB_E_INVALID
+        assert obj.step_count == 3
+    after = (lat.save_raw()[0], b.populations(0), m.populations())
+    for x, y in zip(before, after):
+        assert np.array_equal(x, y)
+    for obj in (lat, b, m):
+        obj.close()
+
+
 def test_health_counts(fm):
     _say("case health")
     p = fm.Params(lattice="d2q9", storage="f64", nx=8, ny=8)
