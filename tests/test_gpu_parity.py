@@ -320,6 +320,22 @@ def test_lattice_beyond_32bit_offsets_runs_two_pass(fm, orc):
                        dict(tau=(1.0, 1.0), tau_d=1.0, G=0.5, kT=1e-5, seed=3), 2, 100, 2e-6)
 
 
+def test_largest_lattice_of_the_fused_kernels(fm, orc):
+    """D3Q19 383^3 FP32, the largest cube the fused kernels take: one
+    species' array is 19 x 383^3 x 4 B = 4.27 GB, so the buffer offsets pass
+    2^31 but stay below 2^32 (a signed 32-bit offset anywhere in the fused
+    path would fail here), with ragged 128x4 tiles (383 = 2 x 128 + 127).
+    Sampled sites against the oracle after 2 steps, as for 256^3."""
+    _say("case 383^3 d3q19 f32 (fused, offsets above 2^31)")
+    assert 19 * 383 ** 3 * 4 > 2 ** 31 and 19 * 383 ** 3 * 4 < 2 ** 32
+    g = fm.Lattice(fm.Params(lattice="d3q19", storage="f32", nx=383, ny=383, nz=383))
+    g.set_tile(128, 4, 0)  # accepted: the fused form runs at this size
+    g.close()
+    del g
+    _sampled_full_size(fm, orc, "d3q19", (383, 383, 383), "f32",
+                       dict(tau=(1.0, 1.0), tau_d=1.0, G=0.5, kT=1e-5, seed=3), 2, 100, 2e-6)
+
+
 @pytest.mark.parametrize("storage,u", [("bf16", 2.0 ** -8), ("f16", 2.0 ** -11)])
 def test_full_size_c3_sampled(fm, orc, storage, u):
     """C3: the C2 workload with 16-bit deviation storage, in the default
