@@ -267,6 +267,8 @@ def main() -> int:
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--multi-only", action="store_true",
                     help="time only the three-species D3Q19 256^3 FP32 workload (for profiling)")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="time only the 512 batched D2Q9 replicas against one launch per replica (for profiling)")
     ap.add_argument("--storage-only", choices=("bf16", "f16"),
                     help="time only the D3Q19 256^3 workload with this 16-bit storage (for profiling)")
     ap.add_argument("--traffic-json", nargs=4, metavar=("FETCH_DB", "WRITE_DB", "COPY_FETCH_DB", "COPY_WRITE_DB"))
@@ -288,6 +290,10 @@ def main() -> int:
     fm.lib()
     torch.cuda.set_device(0)
 
+    if args.batch_only:
+        print(json.dumps({"d2q9_512_replicas_batched_f32": batched(fm, torch, args.steps, args.warmup, plain_steps=10)}),
+              flush=True)
+        return 0
     if args.storage_only:
         print(json.dumps({f"d3q19_256cube_{args.storage_only}_dev":
                           storage16(fm, torch, args.storage_only, args.steps, args.warmup)}), flush=True)
