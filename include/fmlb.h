@@ -217,6 +217,20 @@ fmlb_status fmlb_health(fmlb_ctx *ctx, int64_t counts[2]);
  * for an unsupported shape. */
 fmlb_status fmlb_set_tile(fmlb_ctx *ctx, int tile_x, int tile_y, int march);
 
+/* Offset added (mod 2^32) to the site word of the noise counter: the step at
+ * local site s draws the normals the convention above assigns to site
+ * (s + site_offset) mod 2^32, so the noise stays independent per mode and
+ * site (Sec. VI A) across lattices that share a seed.  A lattice that holds
+ * one slab of a larger lattice (its edge planes copied in from the
+ * neighbouring slabs after every step, as a decomposition across GPUs
+ * would) sets it to the larger lattice's index of its first site minus its
+ * own, mod 2^32, and then draws exactly the noise of the undivided run.
+ * Default 0.  A lattice with a nonzero offset steps in the two-pass form
+ * (density pass, then step; same bits as the fused form), which keeps the
+ * fused kernels free of the extra argument.  Applies to the following steps.
+ * FMLB_E_INVALID outside [0, 2^32). */
+fmlb_status fmlb_set_counter_offset(fmlb_ctx *ctx, int64_t site_offset);
+
 /* Memory reference for the roofline (not part of the method): one launch of
  * a plain copy kernel that reads every population of the current state with
  * the pull offsets of a step (one site per thread, workgroups in row order)

@@ -90,6 +90,7 @@ _SIGNATURES = {
     "fmlb_load_raw": (ctypes.c_int32, [_vp, _vp, ctypes.c_size_t, ctypes.c_int64]),
     "fmlb_health": (ctypes.c_int32, [_vp, _i64p]),
     "fmlb_set_tile": (ctypes.c_int32, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "fmlb_set_counter_offset": (ctypes.c_int32, [_vp, ctypes.c_int64]),
     "fmlb_copy_reference": (ctypes.c_int32, [_vp]),
     "fmlb_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
     "fmlb_last_hip_error": (ctypes.c_int32, []),
@@ -251,6 +252,10 @@ def fmlb_health(ctx: int):
     c = (ctypes.c_int64 * 2)()
     _check("fmlb_health", lib().fmlb_health(_vp(ctx), c))
     return int(c[0]), int(c[1])
+
+
+def fmlb_set_counter_offset(ctx: int, site_offset: int):
+    _check("fmlb_set_counter_offset", lib().fmlb_set_counter_offset(_vp(ctx), int(site_offset)))
 
 
 def fmlb_set_tile(ctx: int, tile_x: int, tile_y: int, march: int):
@@ -507,6 +512,10 @@ class Lattice:
 
     def set_tile(self, tile_x: int = 0, tile_y: int = 0, march: int = 0):
         fmlb_set_tile(self.ctx, tile_x, tile_y, march)
+
+    def set_counter_offset(self, site_offset: int):
+        """Noise-counter site offset (mod 2^32) for a lattice that is one slab of a larger one."""
+        fmlb_set_counter_offset(self.ctx, site_offset)
 
     def copy_reference(self):
         """One launch of the roofline reference copy (state unchanged)."""

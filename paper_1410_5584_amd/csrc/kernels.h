@@ -110,8 +110,10 @@ __global__ __launch_bounds__(256) void density_kernel(StepArgs<L, S> a)
     }
 }
 
+// site_off is added (mod 2^32) to the site word of the noise counter (a
+// lattice that is one slab of a larger one draws the larger one's noise).
 template <class L, class S>
-__global__ __launch_bounds__(256) void step_kernel(StepArgs<L, S> a)
+__global__ __launch_bounds__(256) void step_kernel(StepArgs<L, S> a, uint32_t site_off)
 {
     using Real = typename Storage<S>::Real;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
@@ -135,7 +137,7 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs<L, S> a)
     for (int s = 0; s < 2; ++s) moments<L, Real>(f[s], rho_s[s], j_s[s]);
     // reference density of the stored deviations (0 for absolute storage)
     const Real ref[2] = {Storage<S>::deviation ? a.ref[0] : Real(0), Storage<S>::deviation ? a.ref[1] : Real(0)};
-    collide_site<L, Real>(f, rho_s, j_s, acc, a.ph, ref, Counter{(uint32_t)site, a.step_lo, a.step_hi},
+    collide_site<L, Real>(f, rho_s, j_s, acc, a.ph, ref, Counter{(uint32_t)site + site_off, a.step_lo, a.step_hi},
                           [&](int s, auto &fs) {
 #pragma unroll
                               for (int i = 0; i < L::Q; ++i)

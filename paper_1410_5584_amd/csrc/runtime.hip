@@ -113,6 +113,7 @@ struct fmlb_ctx {
     bool ready;
     int64_t sk_samples, mode_samples;
     int tile_x, tile_y, march;
+    uint32_t site_off;  // noise-counter site offset (two-pass form only)
 };
 
 namespace {
@@ -203,12 +204,12 @@ fmlb_status run_steps(fmlb_ctx *c, int64_t n)
     const SiteGrid sg = site_grid(c->g);
     for (int64_t t = 0; t < n; ++t) {
         StepArgs<L, S> a = step_args<L, S>(c, c->step);
-        if (c->tile_x != 1 && fused_supported<L, S>(c->g, c->tile_x, c->tile_y, c->march)) {
+        if (c->tile_x != 1 && c->site_off == 0 && fused_supported<L, S>(c->g, c->tile_x, c->tile_y, c->march)) {
             HIP_TRY(launch_fused<L, S>(a, c->tile_x, c->tile_y, c->march, c->stream));
         } else {
             hipLaunchKernelGGL((density_kernel<L, S>), sg.grid, sg.block, 0, c->stream, a);
             LAUNCH_CHECK();
-            hipLaunchKernelGGL((step_kernel<L, S>), sg.grid, sg.block, 0, c->stream, a);
+            hipLaunchKernelGGL((step_kernel<L, S>), sg.grid, sg.block, 0, c->stream, a, c->site_off);
             LAUNCH_CHECK();
         }
         c->cur = 1 - c->cur;
@@ -637,6 +638,14 @@ fmlb_status fmlb_health(fmlb_ctx *c, int64_t counts[2])
     if (fmlb_status s2 = sync(c)) return s2;
     counts[0] = (int64_t)h[0];
     counts[1] = (int64_t)h[1];
+    return FMLB_OK;
+}
+
+fmlb_status fmlb_set_counter_offset(fmlb_ctx *c, int64_t site_offset)
+{
+    if (!c) return FMLB_E_NULL;
+    if (site_offset < 0 || site_offset > (int64_t)UINT32_MAX) return FMLB_E_INVALID;
+    c->site_off = (uint32_t)site_offset;
     return FMLB_OK;
 }
 

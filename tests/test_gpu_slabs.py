@@ -9,11 +9,11 @@ owning slab's post-collision populations (here through host copies of the
 raw state; across GPUs a send/receive per face).  The slabs' own planes must
 then equal the undivided lattice bit for bit.
 
-The noise is off: the step keys its noise by the lattice-local site index,
-so a slab would draw the undivided lattice's noise only with the slab's
-global site offset added to the counter (one add per site), which is not
-built.  The streaming, the density ring and the force across the cut, and
-the halo depth, are what this checks.
+With thermal noise on, each slab sets its noise-counter site offset
+(fmlb_set_counter_offset: the undivided lattice's index of its first site
+minus its own), so every site draws the noise it draws in the undivided
+run.  Checked: the streaming, the density ring and the force across the
+cut, the halo depth, and the noise keying.
 """
 import numpy as np
 import pytest
@@ -37,9 +37,9 @@ def _say(*a):
     print(*a, flush=True)
 
 
-def _params(fm, nz, storage):
+def _params(fm, nz, storage, kT=0.0):
     return fm.Params(lattice="d3q19", storage=storage, nx=NX, ny=NY, nz=nz, tau=(0.8, 1.2), tau_d=0.9, G=0.9,
-                     kT=0.0, seed=3)
+                     kT=kT, seed=3)
 
 
 def _planes(raw, storage, nz):
@@ -48,12 +48,12 @@ def _planes(raw, storage, nz):
     return raw.view(dt).reshape(-1, nz, NY * NX)
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32"])
-def test_two_slabs_equal_the_undivided_lattice(fm, storage):
+@pytest.mark.parametrize("storage,kT", [("f64", 0.0), ("f32", 0.0), ("f64", 1e-4), ("f32", 1e-4)])
+def test_two_slabs_equal_the_undivided_lattice(fm, storage, kT):
     import workloads
-    _say("case two z-slabs with halo exchange,", storage)
+    _say("case two z-slabs with halo exchange,", storage, "kT", kT)
     r1, r2 = workloads.initial_density((NZ, NY, NX), "perturbed", seed=12, amplitude=0.05)
-    whole = fm.Lattice(_params(fm, NZ, storage))
+    whole = fm.Lattice(_params(fm, NZ, storage, kT))
     whole.init_density(r1, r2)
     raw0, step0 = whole.save_raw()
     g0 = _planes(raw0, storage, NZ)
@@ -64,7 +64,9 @@ def test_two_slabs_equal_the_undivided_lattice(fm, storage):
     glob = [[(z0 - HALO + e) % NZ for e in range(nze)] for z0 in offsets]   # extended plane -> global plane
     slabs = []
     for k, z0 in enumerate(offsets):
-        lat = fm.Lattice(_params(fm, nze, storage))
+        lat = fm.Lattice(_params(fm, nze, storage, kT))
+        # extended site s holds global site s + (z0 - HALO) * NX * NY on the slab's own planes
+        lat.set_counter_offset(((z0 - HALO) * NX * NY) % 2 ** 32)
         ext = np.ascontiguousarray(g0[:, glob[k], :])
         lat.load_raw(ext.view(np.uint8).reshape(-1), step0)
         slabs.append(lat)
@@ -93,6 +95,32 @@ def test_two_slabs_equal_the_undivided_lattice(fm, storage):
     whole.close()
     for lat in slabs:
         lat.close()
+
+
+def test_counter_offset_range_and_default(fm):
+    """Offsets outside [0, 2^32) are rejected; offset 0 (the default) leaves
+    a run unchanged, and a nonzero offset changes the noise and nothing else
+    (with the noise off the bits are the same)."""
+    lat = fm.Lattice(_params(fm, 4, "f32"))
+    lat.set_counter_offset(0)
+    lat.set_counter_offset(2 ** 32 - 1)
+    for bad in (-1, 2 ** 32):
+        with pytest.raises(fm.FmlbError) as e:
+            lat.set_counter_offset(bad)
+        assert e.value.status == fm.FMLB_E_INVALID
+    lat.close()
+    runs = {}
+    for kT, off in ((1e-4, 0), (1e-4, None), (1e-4, 12345), (0.0, 0), (0.0, 12345)):
+        g = fm.Lattice(_params(fm, 6, "f32", kT))
+        if off is not None:
+            g.set_counter_offset(off)
+        g.init_density(1.0, 0.9)
+        g.step(3)
+        runs[(kT, off)] = g.save_raw()[0]
+        g.close()
+    assert np.array_equal(runs[(1e-4, 0)], runs[(1e-4, None)])
+    assert not np.array_equal(runs[(1e-4, 0)], runs[(1e-4, 12345)])
+    assert np.array_equal(runs[(0.0, 0)], runs[(0.0, 12345)])
 
 
 def test_one_halo_plane_is_not_enough(fm):
