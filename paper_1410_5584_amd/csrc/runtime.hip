@@ -14,6 +14,15 @@
 
 using namespace fmlb;
 
+// BF16 fused steps: instantiated in fused_bf16.hip, which is compiled with
+// its own scheduling strategy.
+namespace fmlb {
+extern template hipError_t launch_fused<D2Q9, __hip_bfloat16>(const StepArgs<D2Q9, __hip_bfloat16> &, int, int, int,
+                                                              hipStream_t);
+extern template hipError_t launch_fused<D3Q19, __hip_bfloat16>(const StepArgs<D3Q19, __hip_bfloat16> &, int, int,
+                                                               int, hipStream_t);
+}  // namespace fmlb
+
 namespace fmlb {
 // Last HIP error of any entry point (shared with the batched entry points).
 thread_local int32_t g_last_hip = 0;
