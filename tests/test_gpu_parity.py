@@ -174,10 +174,11 @@ def test_c2_c3_conservation_over_5000_steps(fm, storage, bound):
     momentum summed in FP64, largest drift over the run.  FP32: about 4e-9
     (6e-10 in 200 steps on the small case above, growing linearly); bound
     1e-7.  16-bit: the lattice demixes (G > 1), and once domains form the
-    round-to-nearest errors of neighbouring sites, whose deviations are
-    nearly equal inside a domain, stop cancelling: measured 2.3e-4 (BF16)
-    and 3.8e-6 (FP16) at 5000 steps after 2e-7 and 1.5e-8 at 1000; bounds
-    4x and 5x those.  The miscible case below has no such drift."""
+    masses drift systematically, far beyond a random walk of independent
+    rounding errors: measured 2.3e-4 (BF16) and 3.8e-6 (FP16) at 5000 steps
+    after 2e-7 and 1.5e-8 at 1000; bounds 4x and 5x those (a regression
+    bound on a known, not fully explained effect).  The miscible case below
+    has no such drift."""
     _say("case c2/c3 conservation, 5000 steps,", storage)
     worst = _drift_over(fm, storage, 256, 1.2, 5000)
     assert np.all(worst <= bound)
