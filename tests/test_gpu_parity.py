@@ -176,9 +176,11 @@ def test_c2_c3_conservation_over_5000_steps(fm, storage, bound):
     1e-7.  16-bit: the lattice demixes (G > 1), and once domains form the
     masses drift systematically, far beyond a random walk of independent
     rounding errors: measured 2.3e-4 (BF16) and 3.8e-6 (FP16) at 5000 steps
-    after 2e-7 and 1.5e-8 at 1000; bounds 4x and 5x those (a regression
-    bound on a known, not fully explained effect).  The miscible case below
-    has no such drift."""
+    after 2e-7 and 1.5e-8 at 1000; bounds 4x and 5x those.  The cause is
+    round-to-nearest of the nearly equal deviations inside a domain, which
+    errs alike at all of its sites (reproduced on the CPU with the oracle in
+    test_oracle_storage16.py, where stochastic rounding removes it).  The
+    miscible case below has no such drift."""
     _say("case c2/c3 conservation, 5000 steps,", storage)
     worst = _drift_over(fm, storage, 256, 1.2, 5000)
     assert np.all(worst <= bound)
