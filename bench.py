@@ -246,9 +246,11 @@ def cpu_baseline(steps: int = 5):
             "sample": f"{steps} steps of the full 256^3 D3Q19 workload in FP64 ({dt:.1f} s)"}
 
 
-def storage16(fm, torch, storage, steps, warmup, mlups_f32=None) -> dict:
-    """The headline workload with BF16 or FP16 deviation storage."""
-    ms16, nsites, _, _, _ = time_steps(fm, torch, storage, steps, warmup)
+def storage16(fm, torch, storage, steps, warmup, mlups_f32=None, stochastic=False) -> dict:
+    """The headline workload with BF16 or FP16 deviation storage, rounded to
+    nearest or (stochastic) with stochastic rounding."""
+    work = dict(WORKLOAD, flags=fm.FMLB_ROUND_STOCHASTIC) if stochastic else WORKLOAD
+    ms16, nsites, _, _, _ = time_steps(fm, torch, storage, steps, warmup, work)
     m16 = nsites * steps / (ms16 / 1e3) / 1e6
     rec = {"value": round(m16, 2), "unit": "MLUPS", "ms_per_step": round(ms16 / steps, 4)}
     if mlups_f32:
@@ -271,6 +273,7 @@ def main() -> int:
                     help="time only the 512 batched D2Q9 replicas against one launch per replica (for profiling)")
     ap.add_argument("--storage-only", choices=("bf16", "f16"),
                     help="time only the D3Q19 256^3 workload with this 16-bit storage (for profiling)")
+    ap.add_argument("--stochastic", action="store_true", help="with --storage-only: stochastic rounding")
     ap.add_argument("--traffic-json", nargs=4, metavar=("FETCH_DB", "WRITE_DB", "COPY_FETCH_DB", "COPY_WRITE_DB"))
     args = ap.parse_args()
     if args.traffic_json:
@@ -295,8 +298,10 @@ def main() -> int:
               flush=True)
         return 0
     if args.storage_only:
-        print(json.dumps({f"d3q19_256cube_{args.storage_only}_dev":
-                          storage16(fm, torch, args.storage_only, args.steps, args.warmup)}), flush=True)
+        tag = "_stochastic" if args.stochastic else ""
+        print(json.dumps({f"d3q19_256cube_{args.storage_only}_dev{tag}":
+                          storage16(fm, torch, args.storage_only, args.steps, args.warmup,
+                                    stochastic=args.stochastic)}), flush=True)
         return 0
     if args.multi_only:
         print(json.dumps({"d3q19_256cube_3species_f32": multi_species(fm, torch, args.steps, args.warmup)}),
@@ -330,6 +335,8 @@ def main() -> int:
         var = {}
         for storage in ("bf16", "f16"):
             var[f"d3q19_256cube_{storage}_dev"] = storage16(fm, torch, storage, args.steps, args.warmup, mlups)
+            var[f"d3q19_256cube_{storage}_dev_stochastic"] = storage16(fm, torch, storage, args.steps, args.warmup,
+                                                                     mlups, stochastic=True)
         ms1, n1, _, _, _ = time_steps(fm, torch, "f32", args.steps, args.warmup, work=C1)
         var["d2q9_1024sq_f32"] = {"value": round(n1 * args.steps / (ms1 / 1e3) / 1e6, 2), "unit": "MLUPS",
                                   "ms_per_step": round(ms1 / args.steps, 4),

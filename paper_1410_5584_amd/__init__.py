@@ -27,7 +27,7 @@ FMLB_E_UNSUPPORTED = -6
 
 FMLB_D2Q9, FMLB_D3Q19 = 0, 1
 FMLB_F64, FMLB_F32, FMLB_BF16_DEV, FMLB_F16_DEV = 0, 1, 2, 3
-FMLB_NOISE_OFF, FMLB_NOISE_NO_SDF = 1, 2
+FMLB_NOISE_OFF, FMLB_NOISE_NO_SDF, FMLB_ROUND_STOCHASTIC = 1, 2, 4
 FMLB_BUF_POPS_A, FMLB_BUF_POPS_B, FMLB_BUF_SCRATCH = 0, 1, 2
 
 LATTICES = {"d2q9": FMLB_D2Q9, "d3q19": FMLB_D3Q19}

@@ -84,6 +84,44 @@ struct BufIO<__half> {
     }
 };
 
+// Stochastic-rounding formats: the same 16-bit words, stored with a hash
+// offset (storage.h).
+template <>
+struct BufIO<bf16_sr> {
+    __device__ static float load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+    {
+        return BufIO<__hip_bfloat16>::load(r, voff, soff);
+    }
+    __device__ static void store(float v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, uint32_t h)
+    {
+        __builtin_amdgcn_raw_buffer_store_b16(bf16_bits_sr(v, h), r, voff, soff, kStoreNonTemporal);
+    }
+};
+
+template <>
+struct BufIO<f16_sr> {
+    __device__ static float load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
+    {
+        return BufIO<__half>::load(r, voff, soff);
+    }
+    __device__ static void store(float v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, uint32_t h)
+    {
+        __builtin_amdgcn_raw_buffer_store_b16(f16_bits_sr(v, h), r, voff, soff, kStoreNonTemporal);
+    }
+};
+
+// Store population sp_pop (= species * Q + i) of a site after the step with
+// counter `step`: round to nearest, or stochastically for the _sr formats.
+template <class S>
+__device__ __forceinline__ void store_stepped(float v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff,
+                                              uint32_t site, uint32_t sp_pop, uint32_t step)
+{
+    if constexpr (Storage<S>::stochastic)
+        BufIO<S>::store(v, r, voff, soff, sr_hash(site, sp_pop, step));
+    else
+        BufIO<S>::store(v, r, voff, soff);
+}
+
 template <class L>
 struct MarchAxes {
     static constexpr bool three_d = L::D == 3;
@@ -258,7 +296,8 @@ __device__ __forceinline__ void fused_tile(const StepArgs<L, S> &a, int t0, int 
 #pragma unroll
                                       for (int i = 0; i < Q; ++i) {
                                           Real v = fs[i];
-                                          BufIO<S>::store(v, rdst[s], voff, (uint32_t)i * pop_bytes);
+                                          store_stepped<S>(v, rdst[s], voff, (uint32_t)i * pop_bytes, site,
+                                                           (uint32_t)(s * Q + i), a.step_lo);
                                       }
                                   });
         }
@@ -312,6 +351,14 @@ struct DmaWord<__hip_bfloat16> {
 template <>
 struct DmaWord<__half> {
     __device__ static float decode(uint32_t r) { return __half2float(__ushort_as_half((unsigned short)r)); }
+};
+
+template <>
+struct DmaWord<bf16_sr> : DmaWord<__hip_bfloat16> {
+};
+
+template <>
+struct DmaWord<f16_sr> : DmaWord<__half> {
 };
 
 // s_waitcnt immediates (gfx9 layout: vmcnt[3:0], expcnt[6:4], lgkmcnt[11:8],
@@ -553,7 +600,8 @@ __device__ __forceinline__ void fused_tile_async(const StepArgs<L, S> &a, int t0
 #pragma unroll
                 for (int i = 0; i < Q; ++i) {
                     Real v = fs[i];
-                    BufIO<S>::store(v, rdst[s], voff, (uint32_t)i * pop_bytes);
+                    store_stepped<S>(v, rdst[s], voff, (uint32_t)i * pop_bytes, site, (uint32_t)(s * Q + i),
+                                     a.step_lo);
                 }
             }
             if constexpr (!D3) {
@@ -838,7 +886,8 @@ __device__ __forceinline__ void fused_tile_rows_body(const StepArgs<L, S> &a, in
 #pragma unroll
                 for (int i = 0; i < Q; ++i) {
                     Real v = fs[i];
-                    BufIO<S>::store(v, rdst[s], voff, (uint32_t)i * pop_bytes);
+                    store_stepped<S>(v, rdst[s], voff, (uint32_t)i * pop_bytes, site, (uint32_t)(s * Q + i),
+                                     a.step_lo);
                 }
             }
         });

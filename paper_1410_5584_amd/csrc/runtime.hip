@@ -74,6 +74,8 @@ bool valid_params(const fmlb_params *p)
     if (!(p->kT >= 0.0) || !std::isfinite(p->kT)) return false;
     if (!std::isfinite(p->G)) return false;
     if (!std::isfinite(p->rho_ref[0]) || !std::isfinite(p->rho_ref[1])) return false;
+    if (p->flags & ~(uint32_t)(FMLB_NOISE_OFF | FMLB_NOISE_NO_SDF | FMLB_ROUND_STOCHASTIC)) return false;
+    if ((p->flags & FMLB_ROUND_STOCHASTIC) && p->storage != FMLB_BF16_DEV && p->storage != FMLB_F16_DEV) return false;
     return true;
 }
 
@@ -136,6 +138,15 @@ T *scr(fmlb_ctx *c, size_t off)
 template <class F>
 fmlb_status dispatch(const fmlb_ctx *c, F &&f)
 {
+    if (c->p.flags & FMLB_ROUND_STOCHASTIC) {
+        switch (c->p.lattice * 4 + c->p.storage) {
+        case FMLB_D2Q9 * 4 + FMLB_BF16_DEV: return f(D2Q9{}, (bf16_sr *)nullptr);
+        case FMLB_D2Q9 * 4 + FMLB_F16_DEV: return f(D2Q9{}, (f16_sr *)nullptr);
+        case FMLB_D3Q19 * 4 + FMLB_BF16_DEV: return f(D3Q19{}, (bf16_sr *)nullptr);
+        case FMLB_D3Q19 * 4 + FMLB_F16_DEV: return f(D3Q19{}, (f16_sr *)nullptr);
+        }
+        return FMLB_E_INVALID;
+    }
     switch (c->p.lattice * 4 + c->p.storage) {
     case FMLB_D2Q9 * 4 + FMLB_F64: return f(D2Q9{}, (double *)nullptr);
     case FMLB_D2Q9 * 4 + FMLB_F32: return f(D2Q9{}, (float *)nullptr);

@@ -7,7 +7,8 @@
 // x-fastest, so every warp-wide access to one population is contiguous.
 //
 // FP32 and the 16-bit formats store the deviation d_i = f_i - w_i
-// rho_ref_sigma (16-bit: rounded to nearest even, widened to FP32 on load);
+// rho_ref_sigma (16-bit: rounded to nearest even, or stochastically for the
+// bf16_sr / f16_sr formats below; widened to FP32 on load);
 // the step kernels update the deviations directly (collide.h), so FP32
 // rounding acts at the scale of the fluctuations, not of w_i rho.  FP64
 // stores absolute values.
@@ -23,10 +24,50 @@ namespace fmlb {
 template <class S>
 struct Storage;
 
+// 16-bit formats whose time steps round the stored deviations
+// stochastically: the bits below the kept ones get a uniform offset from an
+// integer hash of (site, species * Q + population, step), so every rounding
+// is unbiased and the errors of neighbouring sites and of successive steps
+// are independent.  Round-to-nearest errs alike at all sites of a domain of
+// nearly equal deviations, which drifts the species masses of demixed
+// lattices; stochastic rounding does not.  Same bits in memory as BF16 /
+// FP16; initial states and host writes still round to nearest.
+struct bf16_sr {
+    unsigned short x;
+};
+struct f16_sr {
+    unsigned short x;
+};
+
+// 32 hash bits for the stochastic rounding of value (site, sp_pop) at step.
+__device__ __forceinline__ uint32_t sr_hash(uint32_t site, uint32_t sp_pop, uint32_t step)
+{
+    uint32_t h = (site * 0x9E3779B1u) ^ (step * 0x85EBCA77u) ^ (sp_pop * 0xC2B2AE3Du);
+    h ^= h >> 15;
+    h *= 0x2C1B3C6Du;
+    h ^= h >> 12;
+    return h;
+}
+
+// FP32 -> BF16 bits, stochastic: 16 random bits below the kept ones.
+__device__ __forceinline__ unsigned short bf16_bits_sr(float v, uint32_t h)
+{
+    return (unsigned short)((__builtin_bit_cast(uint32_t, v) + (h >> 16)) >> 16);
+}
+
+// FP32 -> FP16 bits, stochastic: 13 random bits below the FP16 mantissa,
+// then the (now exactly representable, for normal FP16 values) conversion.
+__device__ __forceinline__ unsigned short f16_bits_sr(float v, uint32_t h)
+{
+    const uint32_t b = (__builtin_bit_cast(uint32_t, v) + (h >> 19)) & ~0x1FFFu;
+    return __half_as_ushort(__float2half_rn(__builtin_bit_cast(float, b)));
+}
+
 template <>
 struct Storage<double> {
     using Real = double;
     static constexpr bool deviation = false;
+    static constexpr bool stochastic = false;
     __device__ static double load(const double *p, size_t k) { return p[k]; }
     __device__ static void store(double *p, size_t k, double v) { p[k] = v; }
 };
@@ -35,6 +76,7 @@ template <>
 struct Storage<float> {
     using Real = float;
     static constexpr bool deviation = true;
+    static constexpr bool stochastic = false;
     __device__ static float load(const float *p, size_t k) { return p[k]; }
     __device__ static void store(float *p, size_t k, float v) { p[k] = v; }
 };
@@ -43,6 +85,7 @@ template <>
 struct Storage<__hip_bfloat16> {
     using Real = float;
     static constexpr bool deviation = true;
+    static constexpr bool stochastic = false;
     __device__ static float load(const __hip_bfloat16 *p, size_t k) { return __bfloat162float(p[k]); }
     __device__ static void store(__hip_bfloat16 *p, size_t k, float v) { p[k] = __float2bfloat16(v); }
 };
@@ -51,8 +94,32 @@ template <>
 struct Storage<__half> {
     using Real = float;
     static constexpr bool deviation = true;
+    static constexpr bool stochastic = false;
     __device__ static float load(const __half *p, size_t k) { return __half2float(p[k]); }
     __device__ static void store(__half *p, size_t k, float v) { p[k] = __float2half_rn(v); }
+};
+
+template <>
+struct Storage<bf16_sr> {
+    using Real = float;
+    static constexpr bool deviation = true;
+    static constexpr bool stochastic = true;
+    __device__ static float load(const bf16_sr *p, size_t k) { return __builtin_bit_cast(float, (uint32_t)p[k].x << 16); }
+    __device__ static void store(bf16_sr *p, size_t k, float v)
+    {
+        p[k].x = __builtin_bit_cast(unsigned short, __float2bfloat16(v));
+    }
+    __device__ static void store_sr(bf16_sr *p, size_t k, float v, uint32_t h) { p[k].x = bf16_bits_sr(v, h); }
+};
+
+template <>
+struct Storage<f16_sr> {
+    using Real = float;
+    static constexpr bool deviation = true;
+    static constexpr bool stochastic = true;
+    __device__ static float load(const f16_sr *p, size_t k) { return __half2float(__ushort_as_half(p[k].x)); }
+    __device__ static void store(f16_sr *p, size_t k, float v) { p[k].x = __half_as_ushort(__float2half_rn(v)); }
+    __device__ static void store_sr(f16_sr *p, size_t k, float v, uint32_t h) { p[k].x = f16_bits_sr(v, h); }
 };
 
 // Geometry of one periodic lattice.

@@ -55,6 +55,7 @@ def test_required_bytes(fm):
 @pytest.mark.parametrize("bad", [
     dict(tau=(0.5, 1.0)), dict(tau=(1.0, 0.4)), dict(tau_d=0.5), dict(kT=-1e-5),
     dict(nx=0), dict(lattice="d2q9", nz=2), dict(G=float("nan")),
+    dict(storage="f32", flags=4), dict(storage="f64", flags=4), dict(flags=8),
 ])
 def test_invalid_parameters_rejected(fm, bad):
     p = fm.Params(**bad)
