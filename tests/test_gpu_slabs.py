@@ -37,23 +37,26 @@ def _say(*a):
     print(*a, flush=True)
 
 
-def _params(fm, nz, storage, kT=0.0):
+def _params(fm, nz, storage, kT=0.0, flags=0):
     return fm.Params(lattice="d3q19", storage=storage, nx=NX, ny=NY, nz=nz, tau=(0.8, 1.2), tau_d=0.9, G=0.9,
-                     kT=kT, seed=3)
+                     kT=kT, seed=3, flags=flags)
 
 
 def _planes(raw, storage, nz):
     """Raw state as [2 * Q, nz, ny * nx] words of the storage type."""
-    dt = {"f64": np.float64, "f32": np.float32}[storage]
+    dt = {"f64": np.float64, "f32": np.float32, "bf16": np.uint16}[storage]
     return raw.view(dt).reshape(-1, nz, NY * NX)
 
 
-@pytest.mark.parametrize("storage,kT", [("f64", 0.0), ("f32", 0.0), ("f64", 1e-4), ("f32", 1e-4)])
-def test_two_slabs_equal_the_undivided_lattice(fm, storage, kT):
+@pytest.mark.parametrize("storage,kT,flags", [("f64", 0.0, 0), ("f32", 0.0, 0), ("f64", 1e-4, 0), ("f32", 1e-4, 0),
+                                              ("bf16", 1e-4, 4)])
+def test_two_slabs_equal_the_undivided_lattice(fm, storage, kT, flags):
+    """flags 4 = stochastic 16-bit rounding, whose offsets hash the global
+    site index too."""
     import workloads
-    _say("case two z-slabs with halo exchange,", storage, "kT", kT)
+    _say("case two z-slabs with halo exchange,", storage, "kT", kT, "flags", flags)
     r1, r2 = workloads.initial_density((NZ, NY, NX), "perturbed", seed=12, amplitude=0.05)
-    whole = fm.Lattice(_params(fm, NZ, storage, kT))
+    whole = fm.Lattice(_params(fm, NZ, storage, kT, flags))
     whole.init_density(r1, r2)
     raw0, step0 = whole.save_raw()
     g0 = _planes(raw0, storage, NZ)
@@ -64,7 +67,7 @@ def test_two_slabs_equal_the_undivided_lattice(fm, storage, kT):
     glob = [[(z0 - HALO + e) % NZ for e in range(nze)] for z0 in offsets]   # extended plane -> global plane
     slabs = []
     for k, z0 in enumerate(offsets):
-        lat = fm.Lattice(_params(fm, nze, storage, kT))
+        lat = fm.Lattice(_params(fm, nze, storage, kT, flags))
         # extended site s holds global site s + (z0 - HALO) * NX * NY on the slab's own planes
         lat.set_counter_offset(((z0 - HALO) * NX * NY) % 2 ** 32)
         ext = np.ascontiguousarray(g0[:, glob[k], :])
