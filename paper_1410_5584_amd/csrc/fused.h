@@ -117,7 +117,7 @@ __device__ __forceinline__ void store_stepped(float v, __amdgpu_buffer_rsrc_t r,
                                               uint32_t site, uint32_t sp_pop, uint32_t step)
 {
     if constexpr (Storage<S>::stochastic)
-        BufIO<S>::store(v, r, voff, soff, sr_hash(site, sp_pop, step));
+        BufIO<S>::store(v, r, voff, soff, sr_bits(site, sp_pop, step));
     else
         BufIO<S>::store(v, r, voff, soff);
 }

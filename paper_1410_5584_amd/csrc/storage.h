@@ -49,6 +49,15 @@ __device__ __forceinline__ uint32_t sr_hash(uint32_t site, uint32_t sp_pop, uint
     return h;
 }
 
+// Rounding bits (the top 16 are used) of value (site, sp_pop) at step: one
+// hash serves the two values sp_pop = 2m and 2m + 1, its high half for the
+// first and its low half for the second.
+__device__ __forceinline__ uint32_t sr_bits(uint32_t site, uint32_t sp_pop, uint32_t step)
+{
+    const uint32_t h = sr_hash(site, sp_pop >> 1, step);
+    return (sp_pop & 1u) ? h << 16 : h;
+}
+
 // FP32 -> BF16 bits, stochastic: 16 random bits below the kept ones.
 __device__ __forceinline__ unsigned short bf16_bits_sr(float v, uint32_t h)
 {

@@ -5,7 +5,7 @@ hash of (site, species * Q + population, step) below the kept bits, instead
 of to nearest even.  Checked: agreement with the FP64 oracle to the 16-bit
 bound (one unit of the last place instead of half a unit), the same bits in
 every launch shape and in the two-pass form (the hash depends only on the
-site, the population and the step), and, at the C2 coupling where the
+site, the population and the step; one hash serves two values), and, at the C2 coupling where the
 lattice demixes, species masses that no longer drift systematically
 (round-to-nearest: 2.3e-4 of the total over 5000 steps with BF16).
 """
