@@ -275,7 +275,8 @@ int32_t fmlb_last_hip_error(void);
 typedef struct fmlb_batch fmlb_batch;
 
 /* Bytes of buffer `which` (FMLB_BUF_*) for n replicas p[0..n-1]; 0 if any
- * p[r] is not a valid D2Q9 / FMLB_F32 lattice or n is outside [1, 65535]. */
+ * p[r] is not a valid D2Q9 / FMLB_F32 lattice (flags: FMLB_NOISE_* bits only)
+ * or n is outside [1, 65535]. */
 size_t fmlb_batch_required_bytes(const fmlb_params *p, int n, int which);
 
 /* Borrow three 256-byte-aligned device buffers of at least the required
@@ -363,7 +364,7 @@ typedef struct fmlb_multi_params {
     double kT;                     /* >= 0                                           */
     double rho_ref[FMLB_MAX_SPECIES]; /* reference densities of the FP32 deviations  */
     uint64_t seed;
-    uint32_t flags;                /* FMLB_NOISE_* bits                              */
+    uint32_t flags;                /* FMLB_NOISE_* bits; others: FMLB_E_INVALID       */
 } fmlb_multi_params;
 
 typedef struct fmlb_multi fmlb_multi;

@@ -63,6 +63,7 @@ struct BatchItem {
 bool valid_replica(const fmlb_params &p)
 {
     if (p.lattice != FMLB_D2Q9 || p.storage != FMLB_F32) return false;
+    if (p.flags & ~(uint32_t)(FMLB_NOISE_OFF | FMLB_NOISE_NO_SDF)) return false;
     if (p.nx < 1 || p.ny < 1 || p.nz != 1) return false;
     if (p.nx > 65535 * kMinTile || p.ny > 65535) return false;
     if ((double)p.nx * p.ny * kQ * 2 * 4 >= 4294967295.0) return false;

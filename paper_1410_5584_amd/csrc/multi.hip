@@ -40,6 +40,7 @@ bool valid_multi(const fmlb_multi_params *p)
     if (!p) return false;
     if (p->lattice != FMLB_D2Q9 && p->lattice != FMLB_D3Q19) return false;
     if (p->storage != FMLB_F64 && p->storage != FMLB_F32) return false;
+    if (p->flags & ~(uint32_t)(FMLB_NOISE_OFF | FMLB_NOISE_NO_SDF)) return false;
     if (p->nspecies < 2 || p->nspecies > FMLB_MAX_SPECIES) return false;
     if (p->nx < 1 || p->ny < 1 || p->nz < 1) return false;
     if (p->lattice == FMLB_D2Q9 && p->nz != 1) return false;

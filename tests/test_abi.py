@@ -94,7 +94,7 @@ def test_batch_required_bytes(fm):
 
 @pytest.mark.parametrize("bad", [
     dict(lattice="d3q19", nz=4), dict(storage="f64"), dict(storage="bf16"), dict(nz=2),
-    dict(tau=(0.5, 1.0)), dict(kT=-1.0), dict(nx=0),
+    dict(tau=(0.5, 1.0)), dict(kT=-1.0), dict(nx=0), dict(flags=4), dict(flags=8),
 ])
 def test_batch_invalid_replica_rejected(fm, bad):
     reps = [_rep(fm), _rep(fm, **bad)]
@@ -122,6 +122,7 @@ def test_multi_required_bytes(fm):
 @pytest.mark.parametrize("bad", [
     dict(nspecies=1), dict(nspecies=5), dict(storage="bf16"), dict(tau=(1.0, 0.5, 1.0)),
     dict(G=((0.0, 0.3, 0.2), (0.31, 0.0, 0.1), (0.2, 0.1, 0.0))), dict(lattice="d2q9", nz=2), dict(kT=-1.0),
+    dict(flags=4), dict(flags=8),
 ])
 def test_multi_invalid_parameters_rejected(fm, bad):
     kw = dict(nspecies=3, G=((0.0, 0.3, 0.2), (0.3, 0.0, 0.1), (0.2, 0.1, 0.0)))
