@@ -172,9 +172,13 @@ fmlb_status fmlb_global_sums(fmlb_ctx *ctx, double *out);
  * f_bar_i, Eq. (80)), in FP64.  Asynchronous. */
 fmlb_status fmlb_mode_accumulate(fmlb_ctx *ctx);
 
-/* out[2][Q] = (<m_a^2> - <m_a>^2) / (N_a mu rho_ref_sigma), the
+/* out[2][Q] = (<m_a^2> - <m_a>^2) / (N_a mu <rho_sigma>), the
  * equipartition ratio of Eq. (50) (1 in equilibrium), from the running sums;
- * n_samples = number of accumulated snapshots.  Synchronises. */
+ * <rho_sigma> is the sampled mean density (the mean of mode 0 over sites and
+ * snapshots; NaN for a species whose mean density is not positive) and
+ * n_samples the number of accumulated snapshots.  FMLB_E_INVALID when
+ * k_B T = 0 (the ratio is undefined), FMLB_E_STATE before any accumulate.
+ * Synchronises. */
 fmlb_status fmlb_mode_variances(fmlb_ctx *ctx, double *out, int64_t *n_samples);
 
 /* Structure factors (Sec. VI A): add |X_hat(k)|^2 / sites-type products of
@@ -326,8 +330,9 @@ fmlb_status fmlb_batch_global_sums(fmlb_batch *b, int r, double *out);
 
 /* Equipartition statistics of every replica: accumulate adds the current
  * state's per-replica mode sums (as fmlb_mode_accumulate); variances gives
- * replica r's out[2][9] normalised with its own k_B T and rho_ref (as
- * fmlb_mode_variances); reset clears every replica's sums. */
+ * replica r's out[2][9] normalised with its own k_B T and sampled mean
+ * densities (as fmlb_mode_variances, with the same errors); reset clears
+ * every replica's sums. */
 fmlb_status fmlb_batch_mode_accumulate(fmlb_batch *b);
 fmlb_status fmlb_batch_mode_variances(fmlb_batch *b, int r, double *out, int64_t *n_samples);
 fmlb_status fmlb_batch_reset_modes(fmlb_batch *b);

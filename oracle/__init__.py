@@ -25,6 +25,7 @@ _HDR = os.path.join(_HERE, "flbe_oracle.h")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 D2Q9, D3Q19 = 0, 1
+MAX_NORMALS = 128  # ORC_MAX_NORMALS
 NOISE_OFF, NOISE_NO_SDF = 1, 2
 
 
@@ -71,6 +72,7 @@ def lib():
                                 ctypes.POINTER(ctypes.c_int), dp, dp, dp]
         L.orc_philox4x32_10.argtypes = [ctypes.POINTER(ctypes.c_uint32)] * 3
         L.orc_uniforms.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int64, ctypes.c_int, dp]
+        L.orc_normals.restype = ctypes.c_int
         L.orc_normals.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int64, ctypes.c_int, dp]
         L.orc_create.restype = ctypes.c_void_p
         L.orc_create.argtypes = [ctypes.POINTER(_Params)]
@@ -141,9 +143,10 @@ def uniforms(seed: int, site: int, step: int, n: int) -> np.ndarray:
 
 
 def normals(seed: int, site: int, step: int, K: int) -> np.ndarray:
-    z = np.zeros(K)
-    lib().orc_normals(seed, site, step, K, _dp(z))
-    return z
+    z = np.zeros(max(K, 1))
+    if lib().orc_normals(seed, site, step, K, _dp(z)) != 0:
+        raise ValueError(f"orc_normals: K = {K} outside [0, {MAX_NORMALS}]")
+    return z[:K]
 
 
 @dataclass

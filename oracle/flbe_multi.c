@@ -37,7 +37,7 @@
 #include <string.h>
 
 #define QMAX 19
-#define KMAX 128
+#define KMAX ORC_MAX_NORMALS
 
 struct orc_multi {
     orc_multi_params p;
@@ -83,6 +83,10 @@ orc_multi *orc_multi_create(const orc_multi_params *p)
     for (int a = 0; a < s->Q; ++a)
         for (int i = 0; i < s->Q; ++i) s->T[a][i] = T[a * s->Q + i];
     s->K = s->D * (s->N - 1) + s->N * (s->Q - s->D - 1);
+    if (s->K > KMAX) {
+        free(s);
+        return NULL;
+    }
     s->nsites = (int64_t)p->nx * p->ny * p->nz;
     const size_t nf = (size_t)s->N * s->Q * s->nsites;
     s->f = (double *)calloc(nf, sizeof(double));
@@ -240,10 +244,8 @@ static void multi_collide_site(const orc_multi *s, int64_t r, double fstar[ORC_M
 
     const int noisy = (p->kT > 0.0) && !(p->flags & ORC_NOISE_OFF);
     double z[KMAX];
-    if (noisy)
-        orc_normals(p->seed, (uint32_t)r, s->step, s->K, z);
-    else
-        for (int k = 0; k < s->K; ++k) z[k] = 0.0;
+    if (!noisy || orc_normals(p->seed, (uint32_t)r, s->step, s->K, z) != 0)
+        for (int k = 0; k < s->K; ++k) z[k] = 0.0; /* K <= KMAX: checked by orc_multi_create */
     const double mu = 3.0 * p->kT;
     const double lam_d = 1.0 / p->tau_d;
 

@@ -256,13 +256,10 @@ void orc_uniforms(uint64_t seed, uint32_t site, int64_t step, int n, double *u)
  * pairs of uniforms (Sec. VI A: independent Gaussian noise per mode and site,
  * Box-Muller):  z_2p = sqrt(-2 ln u_2p) cos(2 pi u_2p+1),
  *               z_2p+1 = sqrt(-2 ln u_2p) sin(2 pi u_2p+1). */
-void orc_normals(uint64_t seed, uint32_t site, int64_t step, int K, double *z)
+int orc_normals(uint64_t seed, uint32_t site, int64_t step, int K, double *z)
 {
-    double u[128]; /* up to 128 normals: D3Q19 with 4 species needs 69 */
-    if (K > 128) {
-        for (int k = 0; k < K; ++k) z[k] = NAN;
-        return;
-    }
+    double u[ORC_MAX_NORMALS]; /* 2 ceil(K / 2) <= ORC_MAX_NORMALS uniforms (the bound is even) */
+    if (K < 0 || K > ORC_MAX_NORMALS || !z) return -1;
     const int pairs = (K + 1) / 2;
     orc_uniforms(seed, site, step, 2 * pairs, u);
     const double two_pi = 6.283185307179586476925286766559;
@@ -272,6 +269,7 @@ void orc_normals(uint64_t seed, uint32_t site, int64_t step, int K, double *z)
         z[2 * p] = r * cos(th);
         if (2 * p + 1 < K) z[2 * p + 1] = r * sin(th);
     }
+    return 0;
 }
 
 /* ------------------------------------------------------------------------- */
@@ -291,6 +289,10 @@ orc_sim *orc_create(const orc_params *p)
     double T[QMAX * QMAX];
     s->Q = orc_basis(p->lattice, &s->D, c, s->w, T, s->N);
     s->K = s->D + SPECIES * (s->Q - s->D - 1);
+    if (s->K > ORC_MAX_NORMALS) {
+        free(s);
+        return NULL;
+    }
     for (int i = 0; i < s->Q; ++i)
         for (int k = 0; k < 3; ++k) s->c[i][k] = c[3 * i + k];
     for (int a = 0; a < s->Q; ++a)
@@ -436,11 +438,9 @@ static void collide_site(const orc_sim *s, int64_t r, double fstar[2][QMAX])
 
     /* Thermal noise (Eq. (74)); mu = k_B T / c_s^2 with c_s^2 = 1/3 (Eq. (18)). */
     const int noisy = (p->kT > 0.0) && !(p->flags & ORC_NOISE_OFF);
-    double z[64];
-    if (noisy)
-        orc_normals(p->seed, (uint32_t)r, s->step, s->K, z);
-    else
-        for (int k = 0; k < s->K; ++k) z[k] = 0.0;
+    double z[ORC_MAX_NORMALS];
+    if (!noisy || orc_normals(p->seed, (uint32_t)r, s->step, s->K, z) != 0)
+        for (int k = 0; k < s->K; ++k) z[k] = 0.0; /* K <= ORC_MAX_NORMALS: checked by orc_create */
     const double mu = 3.0 * p->kT;
     const double lam_d = 1.0 / p->tau_d;
     double sig_d = 0.0;

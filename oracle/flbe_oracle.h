@@ -53,8 +53,10 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
  * (site, step_lo, block, step_hi), key (seed_lo, seed_hi), each 32-bit word
  * split into two 16-bit uniforms, trigonometric Box-Muller on consecutive
  * pairs, i.e. one word per pair of normals). */
+#define ORC_MAX_NORMALS 128 /* normals per site and step (D3Q19 with 4 species: 69) */
 void orc_uniforms(uint64_t seed, uint32_t site, int64_t step, int n, double *u);
-void orc_normals(uint64_t seed, uint32_t site, int64_t step, int K, double *z);
+/* Returns 0, or -1 (z untouched) unless 0 <= K <= ORC_MAX_NORMALS. */
+int orc_normals(uint64_t seed, uint32_t site, int64_t step, int K, double *z);
 
 orc_sim *orc_create(const orc_params *p);
 void orc_destroy(orc_sim *s);

@@ -15,7 +15,8 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libfmlb.so")
+# FMLB_LIBRARY names another build of the same library (e.g. a host-sanitizer build).
+LIB_PATH = os.environ.get("FMLB_LIBRARY") or os.path.join(_HERE, "libfmlb.so")
 
 FMLB_OK = 0
 FMLB_E_INVALID = -1

@@ -563,6 +563,8 @@ fmlb_status fmlb_batch_mode_variances(fmlb_batch *b, int r, double *out, int64_t
 {
     if (!b || !out) return FMLB_E_NULL;
     if (r < 0 || r >= b->n) return FMLB_E_INVALID;
+    if (!(b->p[r].kT > 0.0)) return FMLB_E_INVALID;  // the ratio is defined for k_B T > 0
+    if (b->mode_samples == 0) return FMLB_E_STATE;
     double acc[4 * kQ];
     BATCH_TRY(hipMemcpyAsync(acc, bscr<double>(b, b->lay.modeacc) + (size_t)r * 4 * kQ, sizeof(acc),
                              hipMemcpyDeviceToHost, b->stream));
@@ -570,13 +572,15 @@ fmlb_status fmlb_batch_mode_variances(fmlb_batch *b, int r, double *out, int64_t
     const fmlb_params &p = b->p[r];
     const double cnt = (double)b->mode_samples * (double)b->reps[r].g.nsites;
     const double mu = 3.0 * p.kT;
-    for (int s = 0; s < 2; ++s)
+    for (int s = 0; s < 2; ++s) {
+        const double rho_mean = acc[(s * kQ) * 2] / cnt;  // mean of mode 0 (m_0 = rho)
         for (int a = 0; a < kQ; ++a) {
             const double m1 = acc[(s * kQ + a) * 2] / cnt;
             const double m2 = acc[(s * kQ + a) * 2 + 1] / cnt;
             const double N = (double)D2Q9::Nnum[a] / D2Q9::Nden[a];
-            out[s * kQ + a] = (m2 - m1 * m1) / (N * mu * p.rho_ref[s]);
+            out[s * kQ + a] = rho_mean > 0.0 ? (m2 - m1 * m1) / (N * mu * rho_mean) : NAN;
         }
+    }
     if (n_samples) *n_samples = b->mode_samples;
     return FMLB_OK;
 }

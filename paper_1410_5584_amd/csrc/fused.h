@@ -114,10 +114,10 @@ struct BufIO<f16_sr> {
 // counter `step`: round to nearest, or stochastically for the _sr formats.
 template <class S>
 __device__ __forceinline__ void store_stepped(float v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff,
-                                              uint32_t site, uint32_t sp_pop, uint32_t step)
+                                              uint32_t site, uint32_t sp_pop, uint32_t step, uint32_t k0, uint32_t k1)
 {
     if constexpr (Storage<S>::stochastic)
-        BufIO<S>::store(v, r, voff, soff, sr_bits(site, sp_pop, step));
+        BufIO<S>::store(v, r, voff, soff, sr_bits(site, sp_pop, step, k0, k1));
     else
         BufIO<S>::store(v, r, voff, soff);
 }
@@ -297,7 +297,7 @@ __device__ __forceinline__ void fused_tile(const StepArgs<L, S> &a, int t0, int 
                                       for (int i = 0; i < Q; ++i) {
                                           Real v = fs[i];
                                           store_stepped<S>(v, rdst[s], voff, (uint32_t)i * pop_bytes, site,
-                                                           (uint32_t)(s * Q + i), a.step_lo);
+                                                           (uint32_t)(s * Q + i), a.step_lo, a.ph.key0, a.ph.key1);
                                       }
                                   });
         }
@@ -601,7 +601,7 @@ __device__ __forceinline__ void fused_tile_async(const StepArgs<L, S> &a, int t0
                 for (int i = 0; i < Q; ++i) {
                     Real v = fs[i];
                     store_stepped<S>(v, rdst[s], voff, (uint32_t)i * pop_bytes, site, (uint32_t)(s * Q + i),
-                                     a.step_lo);
+                                     a.step_lo, a.ph.key0, a.ph.key1);
                 }
             }
             if constexpr (!D3) {
@@ -887,7 +887,7 @@ __device__ __forceinline__ void fused_tile_rows_body(const StepArgs<L, S> &a, in
                 for (int i = 0; i < Q; ++i) {
                     Real v = fs[i];
                     store_stepped<S>(v, rdst[s], voff, (uint32_t)i * pop_bytes, site, (uint32_t)(s * Q + i),
-                                     a.step_lo);
+                                     a.step_lo, a.ph.key0, a.ph.key1);
                 }
             }
         });

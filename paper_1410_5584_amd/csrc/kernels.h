@@ -145,7 +145,8 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs<L, S> a, uint32_t si
                                   const size_t k = ((size_t)(s * L::Q + i)) * g.nsites + site;
                                   if constexpr (Storage<S>::stochastic)
                                       Storage<S>::store_sr(a.dst, k, fs[i],
-                                                           sr_bits((uint32_t)site + site_off, (uint32_t)(s * L::Q + i), a.step_lo));
+                                                           sr_bits((uint32_t)site + site_off, (uint32_t)(s * L::Q + i), a.step_lo,
+                                                                   a.ph.key0, a.ph.key1));
                                   else
                                       Storage<S>::store(a.dst, k, fs[i]);
                               }

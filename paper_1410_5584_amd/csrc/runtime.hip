@@ -450,20 +450,25 @@ fmlb_status fmlb_mode_accumulate(fmlb_ctx *c)
 fmlb_status fmlb_mode_variances(fmlb_ctx *c, double *out, int64_t *n_samples)
 {
     if (!c || !out) return FMLB_E_NULL;
+    if (!(c->p.kT > 0.0)) return FMLB_E_INVALID;  // the ratio is defined for k_B T > 0
+    if (c->mode_samples == 0) return FMLB_E_STATE;
     std::vector<double> acc(4 * c->Q);
     HIP_TRY(hipMemcpyAsync(acc.data(), scr<double>(c, c->lay.modeacc), acc.size() * sizeof(double),
                            hipMemcpyDeviceToHost, c->stream));
     if (fmlb_status st = sync(c)) return st;
     const double cnt = (double)c->mode_samples * (double)c->g.nsites;
     const double mu = 3.0 * c->p.kT;
-    for (int s = 0; s < 2; ++s)
+    for (int s = 0; s < 2; ++s) {
+        // sampled mean density of the species: the mean of mode 0 (m_0 = rho)
+        const double rho_mean = acc[(s * c->Q) * 2] / cnt;
         for (int a = 0; a < c->Q; ++a) {
             const double m1 = acc[(s * c->Q + a) * 2] / cnt;
             const double m2 = acc[(s * c->Q + a) * 2 + 1] / cnt;
             const double N = c->p.lattice == FMLB_D2Q9 ? (double)D2Q9::Nnum[a] / D2Q9::Nden[a]
                                                        : (double)D3Q19::Nnum[a] / D3Q19::Nden[a];
-            out[s * c->Q + a] = (m2 - m1 * m1) / (N * mu * c->p.rho_ref[s]);
+            out[s * c->Q + a] = rho_mean > 0.0 ? (m2 - m1 * m1) / (N * mu * rho_mean) : NAN;
         }
+    }
     if (n_samples) *n_samples = c->mode_samples;
     return FMLB_OK;
 }

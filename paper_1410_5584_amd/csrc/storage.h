@@ -26,7 +26,7 @@ struct Storage;
 
 // 16-bit formats whose time steps round the stored deviations
 // stochastically: the bits below the kept ones get a uniform offset from an
-// integer hash of (site, species * Q + population, step), so every rounding
+// integer hash of (site, species * Q + population, step, seed), so every rounding
 // is unbiased and the errors of neighbouring sites and of successive steps
 // are independent.  Round-to-nearest errs alike at all sites of a domain of
 // nearly equal deviations, which drifts the species masses of demixed
@@ -39,35 +39,51 @@ struct f16_sr {
     unsigned short x;
 };
 
-// 32 hash bits for the stochastic rounding of value (site, sp_pop) at step.
-__device__ __forceinline__ uint32_t sr_hash(uint32_t site, uint32_t sp_pop, uint32_t step)
+// 32 hash bits for the stochastic rounding of value (site, sp_pop) at step
+// of a run with Philox key (k0, k1).  The inputs are combined with the three
+// 32-bit primes of xxHash32 (Y. Collet, xxHash specification: PRIME32_1 =
+// 0x9E3779B1, PRIME32_2 = 0x85EBCA77, PRIME32_3 = 0xC2B2AE3D) and mixed by
+// xxHash32's final avalanche (xor-shift 15, multiply PRIME32_2, xor-shift 13,
+// multiply PRIME32_3, xor-shift 16), so runs that differ only in the seed
+// round independently.
+__host__ __device__ __forceinline__ uint32_t sr_hash(uint32_t site, uint32_t sp_pop, uint32_t step, uint32_t k0, uint32_t k1)
 {
-    uint32_t h = (site * 0x9E3779B1u) ^ (step * 0x85EBCA77u) ^ (sp_pop * 0xC2B2AE3Du);
+    uint32_t h = (site * 0x9E3779B1u) ^ (step * 0x85EBCA77u) ^ (sp_pop * 0xC2B2AE3Du) ^ k0 ^ ((k1 << 16) | (k1 >> 16));
     h ^= h >> 15;
-    h *= 0x2C1B3C6Du;
-    h ^= h >> 12;
+    h *= 0x85EBCA77u;
+    h ^= h >> 13;
+    h *= 0xC2B2AE3Du;
+    h ^= h >> 16;
     return h;
 }
 
 // Rounding bits (the top 16 are used) of value (site, sp_pop) at step: one
 // hash serves the two values sp_pop = 2m and 2m + 1, its high half for the
 // first and its low half for the second.
-__device__ __forceinline__ uint32_t sr_bits(uint32_t site, uint32_t sp_pop, uint32_t step)
+__host__ __device__ __forceinline__ uint32_t sr_bits(uint32_t site, uint32_t sp_pop, uint32_t step, uint32_t k0, uint32_t k1)
 {
-    const uint32_t h = sr_hash(site, sp_pop >> 1, step);
+    const uint32_t h = sr_hash(site, sp_pop >> 1, step, k0, k1);
     return (sp_pop & 1u) ? h << 16 : h;
 }
 
 // FP32 -> BF16 bits, stochastic: 16 random bits below the kept ones.
-__device__ __forceinline__ unsigned short bf16_bits_sr(float v, uint32_t h)
+__host__ __device__ __forceinline__ unsigned short bf16_bits_sr(float v, uint32_t h)
 {
     return (unsigned short)((__builtin_bit_cast(uint32_t, v) + (h >> 16)) >> 16);
 }
 
-// FP32 -> FP16 bits, stochastic: 13 random bits below the FP16 mantissa,
-// then the (now exactly representable, for normal FP16 values) conversion.
-__device__ __forceinline__ unsigned short f16_bits_sr(float v, uint32_t h)
+// FP32 -> FP16 bits, stochastic.  Normal FP16 range: 13 random bits below the
+// FP16 mantissa, then the (now exact) conversion.  Below 2^-14 the FP16
+// values are the multiples of 2^-24 (subnormals), coarser than 13 bits below
+// an FP32 mantissa there, so |v| 2^24 gets a uniform offset in [0, 1) and is
+// rounded down to an integer k, stored as k 2^-24 with the sign of v.
+__host__ __device__ __forceinline__ unsigned short f16_bits_sr(float v, uint32_t h)
 {
+    const float a = __builtin_fabsf(v);
+    if (a < 0x1p-14f) {
+        const float k = __builtin_floorf(__builtin_fmaf(a, 0x1p24f, (float)(h >> 16) * 0x1p-16f));
+        return __half_as_ushort(__float2half_rn(__builtin_copysignf(k * 0x1p-24f, v)));
+    }
     const uint32_t b = (__builtin_bit_cast(uint32_t, v) + (h >> 19)) & ~0x1FFFu;
     return __half_as_ushort(__float2half_rn(__builtin_bit_cast(float, b)));
 }

@@ -123,6 +123,46 @@ def test_parity_16bit_deviation(fm, orc, storage, tol, lattice, shape):
     assert err <= tol
 
 
+INTERFACE = dict(tau=(1.0, 1.0), tau_d=1.0, G=1.5, kT=1e-5, seed=9)
+
+
+@pytest.mark.parametrize("lattice,shape,width,storage,steps,tol", [
+    ("d2q9", (1, 32, 100), 50, "f64", 200, 1e-12),
+    ("d2q9", (1, 32, 100), 50, "f32", 200, 2e-5),
+    ("d3q19", (6, 5, 40), 20, "f64", 60, 1e-12),
+    ("d3q19", (4, 4, 256), 128, "f32", 100, 2e-5),
+])
+def test_interface_regime_parity(fm, orc, lattice, shape, width, storage, steps, tol):
+    """The non-homogeneous regime of Sec. VI B: G = 1.5, a stripe of species 1
+    at 2.3 in species 2 at 0.06 (and the reverse outside), k_B T = 1e-5,
+    all rates 1.  Steep interfaces form from the sharp start, the lattice
+    force of Eq. (87) acts across them, the noise amplitudes use local
+    densities down to 0.06 (Sec. VII), and with FP32 deviation storage
+    (rho_ref = 1) the stored deviations are of order one.  The D3Q19 FP32
+    case (x rows of 256) runs the full-width-row kernel of the benchmark.
+    FP64: 1e-12 of max |f| as for every FP64 case.  FP32: the same 2e-5 as
+    the homogeneous FP32 cases."""
+    import workloads
+    nz, ny, nx = shape
+    _say("case interface", lattice, shape, storage, steps)
+    r1, r2 = workloads.stripe_density(nx, ny * nz, width, 2.3, 0.06)
+    r1, r2 = r1.reshape(shape), r2.reshape(shape)
+    g = fm.Lattice(fm.Params(lattice=lattice, storage=storage, nx=nx, ny=ny, nz=nz, **INTERFACE))
+    g.init_density(r1, r2)
+    o = orc.Sim(orc.Params(lattice=0 if lattice == "d2q9" else 1, nx=nx, ny=ny, nz=nz, **INTERFACE))
+    o.init_density(r1, r2)
+    g.step(steps)
+    o.step(steps)
+    fo = o.populations()
+    err = _relerr(g.populations(), fo)
+    rho = fo.sum(axis=1)
+    _say("max rel diff", err, "densities", float(rho.min()), float(rho.max()))
+    assert rho.max() > 2.0 and rho.min() < 0.2  # the interface regime was reached
+    assert err <= tol
+    assert tuple(int(x) for x in g.health()) == (0, 0)
+    g.close()
+
+
 def test_conservation_on_gpu(fm):
     """Masses and momentum over 200 steps at tau != 1.  FP64: roundoff.
     FP32 stores deviations from w_i rho_ref and updates them directly, so the
@@ -217,12 +257,18 @@ def test_checkpoint_and_split_steps_bitwise(fm):
     assert np.array_equal(a, b)
 
 
-def test_observables_match_oracle(fm, orc):
+@pytest.mark.parametrize("lattice, shape", [("d2q9", (1, 24, 32)), ("d3q19", (16, 8, 6)), ("d3q19", (5, 16, 12))])
+def test_observables_match_oracle(fm, orc, lattice, shape):
     """Moments, global sums, one-snapshot structure factors and mode sums of
-    the same FP64 state on both sides."""
-    _say("case observables")
-    shape = (1, 24, 32)
-    g, o = _pair(fm, orc, "d2q9", shape, "f64", tau=(0.8, 1.2), tau_d=1.0, G=0.5, kT=1e-4, seed=2)
+    the same FP64 state on both sides (Sec. VI A; Eqs. (80), (86), (87)).  The
+    D3Q19 shapes mix power-of-two axes (the FFT path of the line transforms)
+    with other lengths (the direct-sum path) on every axis, so the z-axis
+    transform, the z components of j and v_b and the D3Q19 mode sums are all
+    covered."""
+    _say(f"case observables {lattice} {shape}")
+    g, o = _pair(fm, orc, lattice, shape, "f64", tau=(0.8, 1.2), tau_d=1.0, G=0.5, kT=1e-4, seed=2)
+    D = 2 if lattice == "d2q9" else 3
+    Q = 9 if lattice == "d2q9" else 19
     g.step(30)
     o.step(30)
     rho_o, j_o, F_o = o.moments()
@@ -231,31 +277,51 @@ def test_observables_match_oracle(fm, orc):
     assert np.max(np.abs(j_g - j_o)) < 1e-12
     s = g.global_sums()
     assert s[:2] == pytest.approx(rho_o.reshape(2, -1).sum(1), rel=1e-13)
-    assert np.allclose(s[2:], j_o.reshape(2, 2, -1).sum(2).sum(0), atol=1e-12)
+    assert np.allclose(s[2:], j_o.reshape(2, D, -1).sum(2).sum(0), atol=1e-12)
     g.sk_accumulate()
     checks = {
-        "rho1rho1": orc.structure_factor(rho_o[0, 0]),
-        "rho2rho2": orc.structure_factor(rho_o[1, 0]),
-        "rho1rho2": orc.structure_factor(rho_o[0, 0], rho_o[1, 0]),
-        "j1j1": 0.5 * sum(orc.structure_factor(j_o[0, a, 0]) for a in range(2)),
-        "j2j2": 0.5 * sum(orc.structure_factor(j_o[1, a, 0]) for a in range(2)),
-        "j1j2": 0.5 * sum(orc.structure_factor(j_o[0, a, 0], j_o[1, a, 0]) for a in range(2)),
+        "rho1rho1": orc.structure_factor(rho_o[0]),
+        "rho2rho2": orc.structure_factor(rho_o[1]),
+        "rho1rho2": orc.structure_factor(rho_o[0], rho_o[1]),
+        "j1j1": sum(orc.structure_factor(j_o[0, a]) for a in range(D)) / D,
+        "j2j2": sum(orc.structure_factor(j_o[1, a]) for a in range(D)) / D,
+        "j1j2": sum(orc.structure_factor(j_o[0, a], j_o[1, a]) for a in range(D)) / D,
     }
     vb = (j_o[0] + j_o[1] + 0.5 * (F_o[0] + F_o[1])) / (rho_o[0] + rho_o[1])
-    checks["vbvb"] = 0.5 * sum(orc.structure_factor(vb[a, 0]) for a in range(2))
+    checks["vbvb"] = sum(orc.structure_factor(vb[a]) for a in range(D)) / D
     for name, ref in checks.items():
         got, n = g.sk(name)
         assert n == 1
-        got = got[0]
         ref = ref.copy()
-        ref[0, 0] = 0.0
+        ref.flat[0] = 0.0
+        assert got.shape == ref.shape
         assert np.max(np.abs(got - ref)) <= 1e-9 * np.max(np.abs(ref)), name
     g.mode_accumulate()
     ratios, n = g.mode_variances()
-    m = o.mode_moments().reshape(2, 9, -1)
+    assert n == 1
+    m = o.mode_moments().reshape(2, Q, -1)
     var = m.var(axis=2)
-    ref = var / (o.N * 3 * 1e-4 * 1.0)
+    rho_mean = rho_o.reshape(2, -1).mean(axis=1)
+    ref = var / (o.N[None, :] * 3 * 1e-4 * rho_mean[:, None])
     assert np.allclose(ratios, ref, rtol=1e-9)
+    # the z components are not trivially zero in 3D
+    if D == 3:
+        assert np.max(np.abs(j_o[:, 2])) > 1e-4 and np.max(checks["vbvb"]) > 0
+
+
+def test_mode_variances_errors(fm):
+    """No snapshot yet: FMLB_E_STATE; k_B T = 0: the ratio is undefined,
+    FMLB_E_INVALID."""
+    _say("case mode variance errors")
+    for kT, status in ((1e-5, fm.FMLB_E_STATE), (0.0, fm.FMLB_E_INVALID)):
+        g = fm.Lattice(fm.Params(lattice="d2q9", storage="f32", nx=8, ny=6, kT=kT))
+        g.init_density(1.0, 1.0)
+        if kT == 0.0:
+            g.mode_accumulate()
+        with pytest.raises(fm.FmlbError) as e:
+            g.mode_variances()
+        assert e.value.status == status
+        g.close()
 
 
 def test_zero_and_negative_step_counts(fm):
