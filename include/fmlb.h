@@ -195,6 +195,26 @@ fmlb_status fmlb_sk_accumulate(fmlb_ctx *ctx);
  * NULL.  FMLB_E_INVALID for an unknown `which`.  Synchronises. */
 fmlb_status fmlb_sk_get(fmlb_ctx *ctx, int which, double *out, int64_t *n_samples);
 
+/* For callers that cannot allocate device memory or call an allocator (code
+ * under HIP graph capture, allocation-free serving loops): the accumulation
+ * of fmlb_sk_accumulate without a context.  The work arrays (48 bytes per
+ * site) live in a static device array of the library, one per GPU, of
+ * FMLB_SK_STATIC_MAX_SITES * 48 bytes (48 MiB), held until the process ends.
+ *   p:    the lattice, storage and rho_ref of the state (validated as by
+ *         fmlb_create).
+ *   pops: device, the stored state as a context keeps it (pull layout,
+ *         [2][Q][sites] values of p->storage; the bytes fmlb_save_raw returns).
+ *   acc:  device, [7][sites] doubles owned and cleared by the caller; the
+ *         seven quantities of fmlb_sk_accumulate (same order and k layout)
+ *         are added to it, so acc / n_snapshots is what fmlb_sk_get returns.
+ * Asynchronous on hip_stream.  FMLB_E_SIZE above FMLB_SK_STATIC_MAX_SITES
+ * sites, FMLB_E_UNSUPPORTED for an axis longer than 2048.  Nothing is
+ * allocated.  Calls that overlap on one GPU share the static array and race;
+ * a call may start once the previous call on that GPU has completed (stream
+ * order suffices). */
+#define FMLB_SK_STATIC_MAX_SITES (1 << 20)
+fmlb_status fmlb_sk_accumulate_static(const fmlb_params *p, const void *pops, double *acc, void *hip_stream);
+
 /* Clear the structure-factor and mode accumulators.  Asynchronous. */
 fmlb_status fmlb_reset_accumulators(fmlb_ctx *ctx);
 

@@ -83,6 +83,7 @@ _SIGNATURES = {
     "fmlb_mode_accumulate": (ctypes.c_int32, [_vp]),
     "fmlb_mode_variances": (ctypes.c_int32, [_vp, _dp, _i64p]),
     "fmlb_sk_accumulate": (ctypes.c_int32, [_vp]),
+    "fmlb_sk_accumulate_static": (ctypes.c_int32, [_pp, _vp, _vp, _vp]),
     "fmlb_sk_get": (ctypes.c_int32, [_vp, ctypes.c_int, _dp, _i64p]),
     "fmlb_reset_accumulators": (ctypes.c_int32, [_vp]),
     "fmlb_get_populations": (ctypes.c_int32, [_vp, _dp, ctypes.c_size_t]),
@@ -217,6 +218,15 @@ def fmlb_mode_variances(ctx: int, out: np.ndarray) -> int:
 
 def fmlb_sk_accumulate(ctx: int):
     _check("fmlb_sk_accumulate", lib().fmlb_sk_accumulate(_vp(ctx)))
+
+
+SK_STATIC_MAX_SITES = 1 << 20  # FMLB_SK_STATIC_MAX_SITES
+
+
+def fmlb_sk_accumulate_static(params, pops: int, acc: int, stream: int):
+    """params: fmlb_params; pops, acc, stream: device pointers / HIP stream handle."""
+    _check("fmlb_sk_accumulate_static",
+           lib().fmlb_sk_accumulate_static(ctypes.byref(params), _vp(pops), _vp(acc), _vp(stream)))
 
 
 def fmlb_sk_get(ctx: int, which: int, out: np.ndarray) -> int:

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <type_traits>
 #include <vector>
 
@@ -251,9 +252,8 @@ fmlb_status sync(fmlb_ctx *c)
 }
 
 // Forward DFT of a complex lattice field along every axis of length > 1.
-fmlb_status dft_field(fmlb_ctx *c, double2 *A)
+fmlb_status dft_field(const Geom &g, hipStream_t stream, double2 *A)
 {
-    const Geom &g = c->g;
     const int dims[3] = {g.nx, g.ny, g.nz};
     for (int ax = 0; ax < 3; ++ax) {
         const int L = dims[ax];
@@ -280,10 +280,98 @@ fmlb_status dft_field(fmlb_ctx *c, double2 *A)
         }
         const int threads = L >= 512 ? 256 : (L >= 128 ? 128 : 64);
         const size_t lds = 2 * (size_t)L * sizeof(double2);
-        hipLaunchKernelGGL(dft_lines_kernel, dim3((unsigned)lines), dim3(threads), lds, c->stream, A, L, stride,
+        hipLaunchKernelGGL(dft_lines_kernel, dim3((unsigned)lines), dim3(threads), lds, stream, A, L, stride,
                            (int)inner, inner_stride, outer_stride);
         LAUNCH_CHECK();
     }
+    return FMLB_OK;
+}
+
+// Bytes of work arrays the structure-factor accumulation needs per site:
+// the densities of both species (FP64 at most, for the force in v_b) and two
+// complex FP64 line-transform buffers.
+constexpr size_t kSkWorkBytesPerSite = 2 * sizeof(double) + 2 * sizeof(double2);
+
+// The structure-factor accumulation of one snapshot (Sec. VI A): the seven
+// quantities of fmlb_sk_accumulate are added to acc[7][sites].  rho, A and B
+// are work arrays of 2 * sites Real, sites and sites double2.
+template <class L, class S>
+fmlb_status sk_accumulate_impl(const fmlb_params &p, const Geom &g, hipStream_t stream, const S *src,
+                               typename Storage<S>::Real *rho, double2 *A, double2 *B, double *acc)
+{
+    using Real = typename Storage<S>::Real;
+    const size_t n = g.nsites;
+    constexpr int D = L::D;
+    const Real ref0 = (Real)p.rho_ref[0], ref1 = (Real)p.rho_ref[1];
+    StepArgs<L, S> a{};
+    a.src = src;
+    a.rho = rho;
+    a.g = g;
+    const SiteGrid sg = site_grid(g);
+    hipLaunchKernelGGL((density_kernel<L, S>), sg.grid, sg.block, 0, stream, a);
+    LAUNCH_CHECK();
+    const dim3 gb(stride_blocks(n)), tb(256);
+    auto field = [&](double2 *dst, int kind, int s, int al) -> fmlb_status {
+        hipLaunchKernelGGL((sk_field_kernel<L, S>), gb, tb, 0, stream, src, (const Real *)rho, dst, g, kind, s, al,
+                           -p.G, ref0, ref1);
+        LAUNCH_CHECK();
+        return dft_field(g, stream, dst);
+    };
+    auto accum = [&](const double2 *X, const double2 *Y, int q, double scale) -> fmlb_status {
+        hipLaunchKernelGGL(sk_accum_kernel, gb, tb, 0, stream, X, Y, acc + (size_t)q * n, n, scale);
+        LAUNCH_CHECK();
+        return FMLB_OK;
+    };
+    const double inv_n = 1.0 / (double)n;
+    fmlb_status st;
+    if ((st = field(A, 0, 0, 0))) return st;
+    if ((st = accum(A, A, 0, inv_n))) return st;
+    if ((st = field(B, 0, 1, 0))) return st;
+    if ((st = accum(B, B, 1, inv_n))) return st;
+    if ((st = accum(A, B, 2, inv_n))) return st;
+    for (int al = 0; al < D; ++al) {
+        if ((st = field(A, 1, 0, al))) return st;
+        if ((st = field(B, 1, 1, al))) return st;
+        if ((st = accum(A, A, 3, inv_n / D))) return st;
+        if ((st = accum(B, B, 4, inv_n / D))) return st;
+        if ((st = accum(A, B, 5, inv_n / D))) return st;
+    }
+    for (int al = 0; al < D; ++al) {
+        if ((st = field(A, 2, 0, al))) return st;
+        if ((st = accum(A, A, 6, inv_n / D))) return st;
+    }
+    return FMLB_OK;
+}
+
+constexpr size_t kSkStaticBytes = (size_t)FMLB_SK_STATIC_MAX_SITES * kSkWorkBytesPerSite;
+
+}  // namespace
+
+// Work arrays of fmlb_sk_accumulate_static: one copy per GPU, held until the
+// process ends.  Host code reaches it only through the device address that
+// hipGetSymbolAddress returns for the current device (static_scratch()).
+static __device__ __align__(256) unsigned char scratch[kSkStaticBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void *g_scratch_ptr[kMaxDevices];
+
+// Device address of `scratch` on the current device (looked up once per device).
+fmlb_status static_scratch(void **out)
+{
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return FMLB_E_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return FMLB_E_HIP;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
     return FMLB_OK;
 }
 
@@ -478,53 +566,42 @@ fmlb_status fmlb_sk_accumulate(fmlb_ctx *c)
     if (!c) return FMLB_E_NULL;
     if (!c->ready) return FMLB_E_STATE;
     if (c->g.nx > kMaxLine || c->g.ny > kMaxLine || c->g.nz > kMaxLine) return FMLB_E_UNSUPPORTED;
-    const size_t n = c->g.nsites;
     double2 *A = scr<double2>(c, c->lay.skA);
     double2 *B = scr<double2>(c, c->lay.skB);
     double *acc = scr<double>(c, c->lay.skacc);
-    const int D = c->D;
-    return dispatch(c, [&](auto l, auto sp) -> fmlb_status {
+    fmlb_status st = dispatch(c, [&](auto l, auto sp) -> fmlb_status {
         using L = decltype(l);
         using S = std::remove_pointer_t<decltype(sp)>;
         using Real = typename Storage<S>::Real;
-        const S *src = reinterpret_cast<const S *>(c->pops[c->cur]);
-        Real *rho = scr<Real>(c, c->lay.rho);
-        StepArgs<L, S> a = step_args<L, S>(c, c->step);
-        const SiteGrid sg = site_grid(c->g);
-        hipLaunchKernelGGL((density_kernel<L, S>), sg.grid, sg.block, 0, c->stream, a);
-        LAUNCH_CHECK();
-        const dim3 gb(stride_blocks(n)), tb(256);
-        auto field = [&](double2 *dst, int kind, int s, int al) -> fmlb_status {
-            hipLaunchKernelGGL((sk_field_kernel<L, S>), gb, tb, 0, c->stream, src, (const Real *)rho, dst, c->g, kind,
-                               s, al, -c->p.G, ref_of<S>(c, 0), ref_of<S>(c, 1));
-            LAUNCH_CHECK();
-            return dft_field(c, dst);
-        };
-        auto accum = [&](const double2 *X, const double2 *Y, int q, double scale) -> fmlb_status {
-            hipLaunchKernelGGL(sk_accum_kernel, gb, tb, 0, c->stream, X, Y, acc + (size_t)q * n, n, scale);
-            LAUNCH_CHECK();
-            return FMLB_OK;
-        };
-        const double inv_n = 1.0 / (double)n;
-        fmlb_status st;
-        if ((st = field(A, 0, 0, 0))) return st;
-        if ((st = accum(A, A, 0, inv_n))) return st;
-        if ((st = field(B, 0, 1, 0))) return st;
-        if ((st = accum(B, B, 1, inv_n))) return st;
-        if ((st = accum(A, B, 2, inv_n))) return st;
-        for (int al = 0; al < D; ++al) {
-            if ((st = field(A, 1, 0, al))) return st;
-            if ((st = field(B, 1, 1, al))) return st;
-            if ((st = accum(A, A, 3, inv_n / D))) return st;
-            if ((st = accum(B, B, 4, inv_n / D))) return st;
-            if ((st = accum(A, B, 5, inv_n / D))) return st;
-        }
-        for (int al = 0; al < D; ++al) {
-            if ((st = field(A, 2, 0, al))) return st;
-            if ((st = accum(A, A, 6, inv_n / D))) return st;
-        }
-        c->sk_samples += 1;
-        return FMLB_OK;
+        return sk_accumulate_impl<L, S>(c->p, c->g, c->stream, reinterpret_cast<const S *>(c->pops[c->cur]),
+                                        scr<Real>(c, c->lay.rho), A, B, acc);
+    });
+    if (st) return st;
+    c->sk_samples += 1;
+    return FMLB_OK;
+}
+
+fmlb_status fmlb_sk_accumulate_static(const fmlb_params *p, const void *pops, double *acc, void *hip_stream)
+{
+    if (!p || !pops || !acc) return FMLB_E_NULL;
+    if (!valid_params(p)) return FMLB_E_INVALID;
+    const Geom g{p->nx, p->ny, p->nz, (size_t)p->nx * p->ny * p->nz};
+    if (g.nsites > (size_t)FMLB_SK_STATIC_MAX_SITES) return FMLB_E_SIZE;
+    if (g.nx > kMaxLine || g.ny > kMaxLine || g.nz > kMaxLine) return FMLB_E_UNSUPPORTED;
+    void *base = nullptr;
+    if (fmlb_status st = static_scratch(&base)) return st;
+    // work arrays carved from the static array: rho (2 sites x 8 bytes), A, B
+    unsigned char *w = reinterpret_cast<unsigned char *>(base);
+    double2 *A = reinterpret_cast<double2 *>(w + 2 * g.nsites * sizeof(double));
+    double2 *B = A + g.nsites;
+    fmlb_ctx tmp{};
+    tmp.p = *p;
+    return dispatch(&tmp, [&](auto l, auto sp) -> fmlb_status {
+        using L = decltype(l);
+        using S = std::remove_pointer_t<decltype(sp)>;
+        using Real = typename Storage<S>::Real;
+        return sk_accumulate_impl<L, S>(*p, g, reinterpret_cast<hipStream_t>(hip_stream),
+                                        reinterpret_cast<const S *>(pops), reinterpret_cast<Real *>(w), A, B, acc);
     });
 }
 
