@@ -114,7 +114,14 @@ def _events(torch):
     return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
 
-def time_steps(fm, torch, storage: str, steps: int, warmup: int, work=WORKLOAD):
+REFERENCES = (("pull_copy", 0), ("read", 1), ("write", 2), ("copy16", 3))
+
+
+def time_steps(fm, torch, storage: str, steps: int, warmup: int, work=WORKLOAD, windows: int = 0,
+               references: bool = False):
+    """K steps timed as one region on the lattice's stream (the contract),
+    then `windows` more windows of K steps (their median and spread), and
+    the bandwidth references (each timed over K launches)."""
     import workloads
     p = fm.Params(storage=storage, rho_ref=(1.0, 1.0), **work)
     lat = fm.Lattice(p)
@@ -131,18 +138,29 @@ def time_steps(fm, torch, storage: str, steps: int, warmup: int, work=WORKLOAD):
     end.record(stream)
     torch.cuda.synchronize()
     ms = start.elapsed_time(end)
+    win = []
+    for _ in range(windows):
+        start.record(stream)
+        lat.step(steps)
+        end.record(stream)
+        torch.cuda.synchronize()
+        win.append(start.elapsed_time(end) / steps)
     sums = lat.global_sums()
     health = lat.health()
-    # roofline reference: a plain copy with the step's pull addresses
-    lat.copy_reference()
-    start.record(stream)
-    for _ in range(steps):
-        lat.copy_reference()
-    end.record(stream)
-    torch.cuda.synchronize()
-    ms_copy = start.elapsed_time(end)
+    refs = {}
+    if references:
+        for name, kind in REFERENCES:
+            nbytes = lat.bandwidth_reference(kind)
+            start.record(stream)
+            for _ in range(steps):
+                lat.bandwidth_reference(kind)
+            end.record(stream)
+            torch.cuda.synchronize()
+            t = start.elapsed_time(end) / steps
+            refs[name] = {"ms_per_launch": round(t, 4), "bytes": nbytes,
+                          "frac": round(nbytes / (t / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
     lat.close()
-    return ms, p.nx * p.ny * p.nz, sums, health, ms_copy
+    return ms, p.nx * p.ny * p.nz, sums, health, refs, win
 
 
 def batched(fm, torch, steps: int, warmup: int, plain_steps: int):
@@ -224,6 +242,51 @@ def multi_species(fm, torch, steps: int, warmup: int, n: int = 3):
             "note": "two kernels per step (potential pass, then the step): every population is read twice"}
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def c1_end_to_end(fm, torch, steps: int = 10000, every: int = 100):
+    """The C1 run as the workload states it: D2Q9 1024^2 FP32, 1e4 steps,
+    structure factors accumulated every 100 steps, timed whole on the
+    lattice's stream."""
+    import workloads
+    p = fm.Params(storage="f32", rho_ref=(1.0, 1.0), **C1)
+    lat = fm.Lattice(p)
+    r1, r2 = workloads.initial_density((1, p.ny, p.nx), "perturbed", seed=p.seed, amplitude=0.01)
+    lat.init_density(r1, r2)
+    lat.step(every)
+    lat.sk_accumulate()
+    lat.reset_accumulators()
+    start, end = _events(torch)
+    torch.cuda.synchronize()
+    start.record(lat.stream)
+    for _ in range(steps // every):
+        lat.step(every)
+        lat.sk_accumulate()
+    end.record(lat.stream)
+    torch.cuda.synchronize()
+    ms_total = start.elapsed_time(end)
+    start.record(lat.stream)
+    lat.step(steps)
+    end.record(lat.stream)
+    torch.cuda.synchronize()
+    ms_steps = start.elapsed_time(end)
+    n = p.nx * p.ny
+    lat.close()
+    return {"value": round(n * steps / (ms_total / 1e3) / 1e6, 2), "unit": "MLUPS", "steps": steps,
+            "sk_every": every, "ms_total": round(ms_total, 2), "ms_steps_only": round(ms_steps, 2),
+            "sk_share": round(1.0 - ms_steps / ms_total, 4),
+            "ms_per_sk": round((ms_total - ms_steps) / (steps // every), 4)}
+
+
 def cpu_baseline(steps: int = 5):
     """The FP64 oracle (as it stands) on `steps` steps of the full 256^3 workload."""
     import numpy as np
@@ -242,7 +305,7 @@ def cpu_baseline(steps: int = 5):
     dt = time.perf_counter() - t0
     n = int(np.prod(shape))
     return {"value": round(n * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": oracle.num_threads(),
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": cpu_model(), "cpus_online": os.cpu_count(),
             "sample": f"{steps} steps of the full 256^3 D3Q19 workload in FP64 ({dt:.1f} s)"}
 
 
@@ -250,7 +313,7 @@ def storage16(fm, torch, storage, steps, warmup, mlups_f32=None, stochastic=Fals
     """The headline workload with BF16 or FP16 deviation storage, rounded to
     nearest or (stochastic) with stochastic rounding."""
     work = dict(WORKLOAD, flags=fm.FMLB_ROUND_STOCHASTIC) if stochastic else WORKLOAD
-    ms16, nsites, _, _, _ = time_steps(fm, torch, storage, steps, warmup, work)
+    ms16, nsites, _, _, _, _ = time_steps(fm, torch, storage, steps, warmup, work)
     m16 = nsites * steps / (ms16 / 1e3) / 1e6
     rec = {"value": round(m16, 2), "unit": "MLUPS", "ms_per_step": round(ms16 / steps, 4)}
     if mlups_f32:
@@ -264,6 +327,8 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--windows", type=int, default=5,
+                    help="further windows of --steps steps, timed for the median and spread")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
@@ -274,6 +339,8 @@ def main() -> int:
     ap.add_argument("--storage-only", choices=("bf16", "f16"),
                     help="time only the D3Q19 256^3 workload with this 16-bit storage (for profiling)")
     ap.add_argument("--stochastic", action="store_true", help="with --storage-only: stochastic rounding")
+    ap.add_argument("--c1-only", action="store_true",
+                    help="time only the D2Q9 1024^2 run with S(k) every 100 steps (for profiling)")
     ap.add_argument("--traffic-json", nargs=4, metavar=("FETCH_DB", "WRITE_DB", "COPY_FETCH_DB", "COPY_WRITE_DB"))
     args = ap.parse_args()
     if args.traffic_json:
@@ -303,12 +370,16 @@ def main() -> int:
                           storage16(fm, torch, args.storage_only, args.steps, args.warmup,
                                     stochastic=args.stochastic)}), flush=True)
         return 0
+    if args.c1_only:
+        print(json.dumps({"d2q9_1024sq_f32_end_to_end": c1_end_to_end(fm, torch)}), flush=True)
+        return 0
     if args.multi_only:
         print(json.dumps({"d3q19_256cube_3species_f32": multi_species(fm, torch, args.steps, args.warmup)}),
               flush=True)
         return 0
 
-    ms, nsites, sums, health, ms_copy = time_steps(fm, torch, "f32", args.steps, args.warmup)
+    ms, nsites, sums, health, refs, win = time_steps(fm, torch, "f32", args.steps, args.warmup,
+                                                     windows=args.windows, references=True)
     ms_per_step = ms / args.steps
     mlups = nsites * args.steps / (ms / 1e3) / 1e6
     bps = BYTES_PER_SITE[("d3q19", "f32")]
@@ -325,22 +396,26 @@ def main() -> int:
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None if traffic is None else round(traffic),
                      "algorithmic_bytes_per_launch": bps * nsites,
-                     "copy_reference": {
-                         "ms_per_launch": round(ms_copy / args.steps, 4),
-                         "frac": round(bps * nsites / (ms_copy / args.steps / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
-                         "note": "plain copy with the step's pull addresses (fmlb_copy_reference)"}},
+                     "references": dict(refs, note="bandwidth references over the same buffers "
+                                        "(fmlb_bandwidth_reference): pull_copy = the step's pull addresses, "
+                                        "read / write = one direction only, copy16 = unshifted 16-byte copy")},
         "checks": {"mass": [float(sums[0]), float(sums[1])], "health": list(health)},
     }
+    if win:
+        rec["timing"] = {"windows": len(win), "steps_per_window": args.steps,
+                         "median_ms_per_step": round(float(sorted(win)[len(win) // 2]), 4),
+                         "min_ms_per_step": round(min(win), 4), "max_ms_per_step": round(max(win), 4)}
     if not args.no_variants:
         var = {}
         for storage in ("bf16", "f16"):
             var[f"d3q19_256cube_{storage}_dev"] = storage16(fm, torch, storage, args.steps, args.warmup, mlups)
             var[f"d3q19_256cube_{storage}_dev_stochastic"] = storage16(fm, torch, storage, args.steps, args.warmup,
                                                                      mlups, stochastic=True)
-        ms1, n1, _, _, _ = time_steps(fm, torch, "f32", args.steps, args.warmup, work=C1)
+        ms1, n1, _, _, _, _ = time_steps(fm, torch, "f32", args.steps, args.warmup, work=C1)
         var["d2q9_1024sq_f32"] = {"value": round(n1 * args.steps / (ms1 / 1e3) / 1e6, 2), "unit": "MLUPS",
                                   "ms_per_step": round(ms1 / args.steps, 4),
                                   "note": "75 MB per buffer, cache-resident: HBM fraction not meaningful"}
+        var["d2q9_1024sq_f32_end_to_end"] = c1_end_to_end(fm, torch)
         var["d2q9_512_replicas_batched_f32"] = batched(fm, torch, args.steps, args.warmup, plain_steps=10)
         var["d3q19_256cube_3species_f32"] = multi_species(fm, torch, args.steps, args.warmup)
         rec["variants"] = var

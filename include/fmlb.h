@@ -197,9 +197,9 @@ fmlb_status fmlb_sk_get(fmlb_ctx *ctx, int which, double *out, int64_t *n_sample
 
 /* For callers that cannot allocate device memory or call an allocator (code
  * under HIP graph capture, allocation-free serving loops): the accumulation
- * of fmlb_sk_accumulate without a context.  The work arrays (48 bytes per
+ * of fmlb_sk_accumulate without a context.  The work arrays (32 bytes per
  * site) live in a static device array of the library, one per GPU, of
- * FMLB_SK_STATIC_MAX_SITES * 48 bytes (48 MiB), held until the process ends.
+ * FMLB_SK_STATIC_MAX_SITES * 32 bytes (32 MiB), held until the process ends.
  *   p:    the lattice, storage and rho_ref of the state (validated as by
  *         fmlb_create).
  *   pops: device, the stored state as a context keeps it (pull layout,
@@ -275,6 +275,20 @@ fmlb_status fmlb_set_counter_offset(fmlb_ctx *ctx, int64_t site_offset);
  * changed (the other buffer is scratch between steps; the step counter does
  * not advance).  Asynchronous. */
 fmlb_status fmlb_copy_reference(fmlb_ctx *ctx);
+
+/* Further memory references for the roofline (not part of the method), one
+ * launch each over the current population buffer viewed as 16-byte words
+ * (a tail of fewer than 16 bytes is left out):
+ *   FMLB_BW_PULL_COPY  fmlb_copy_reference;
+ *   FMLB_BW_READ       read every word of the state (2048 workgroups);
+ *   FMLB_BW_WRITE      write zeros over the other buffer (256 workgroups);
+ *   FMLB_BW_COPY16     copy the state to the other buffer, unshifted,
+ *                      16-byte words, 4 in flight per thread (256 workgroups).
+ * *bytes (may be NULL) receives the bytes the launch reads plus writes.  The
+ * state is unchanged (the other buffer is scratch between steps).
+ * FMLB_E_INVALID for an unknown kind.  Asynchronous. */
+enum { FMLB_BW_PULL_COPY = 0, FMLB_BW_READ = 1, FMLB_BW_WRITE = 2, FMLB_BW_COPY16 = 3 };
+fmlb_status fmlb_bandwidth_reference(fmlb_ctx *ctx, int kind, double *bytes);
 
 /* Human-readable name of a status code; the last HIP error code of any call. */
 const char *fmlb_status_string(fmlb_status s);

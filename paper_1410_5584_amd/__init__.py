@@ -94,6 +94,7 @@ _SIGNATURES = {
     "fmlb_set_tile": (ctypes.c_int32, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "fmlb_set_counter_offset": (ctypes.c_int32, [_vp, ctypes.c_int64]),
     "fmlb_copy_reference": (ctypes.c_int32, [_vp]),
+    "fmlb_bandwidth_reference": (ctypes.c_int32, [_vp, ctypes.c_int, _dp]),
     "fmlb_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
     "fmlb_last_hip_error": (ctypes.c_int32, []),
     "fmlb_batch_required_bytes": (ctypes.c_size_t, [_pp, ctypes.c_int, ctypes.c_int]),
@@ -352,6 +353,16 @@ def fmlb_copy_reference(ctx: int):
     _check("fmlb_copy_reference", lib().fmlb_copy_reference(_vp(ctx)))
 
 
+FMLB_BW_PULL_COPY, FMLB_BW_READ, FMLB_BW_WRITE, FMLB_BW_COPY16 = 0, 1, 2, 3
+
+
+def fmlb_bandwidth_reference(ctx: int, kind: int) -> float:
+    """Launch one bandwidth reference kernel; returns the bytes it moves."""
+    b = ctypes.c_double()
+    _check("fmlb_bandwidth_reference", lib().fmlb_bandwidth_reference(_vp(ctx), kind, ctypes.byref(b)))
+    return b.value
+
+
 # ---- convenience wrapper: torch-owned buffers, numpy host arrays ------------
 
 def fmlb_multi_required_bytes(p: fmlb_multi_params, which: int) -> int:
@@ -531,6 +542,10 @@ class Lattice:
     def copy_reference(self):
         """One launch of the roofline reference copy (state unchanged)."""
         fmlb_copy_reference(self.ctx)
+
+    def bandwidth_reference(self, kind: int) -> float:
+        """One launch of bandwidth reference `kind` (FMLB_BW_*); returns its bytes."""
+        return fmlb_bandwidth_reference(self.ctx, kind)
 
     def synchronize(self):
         self.stream.synchronize()

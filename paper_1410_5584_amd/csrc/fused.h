@@ -29,6 +29,7 @@
 #pragma once
 
 #include <type_traits>
+#include <utility>
 
 #include "kernels.h"
 
@@ -624,6 +625,74 @@ __device__ __forceinline__ void fused_tile_async(const StepArgs<L, S> &a, int t0
 }
 
 // ---------------------------------------------------------------------------
+// Layout of the 16-byte row pulls of the full-width tiles.  A wave owns 64
+// consecutive sites x0 .. x0+63 of one lattice row; population i of that
+// slice is pulled from x0 - c_x(i) .. x0 + 63 - c_x(i), which the aligned
+// 16-byte chunks (EPC elements each) from x0 - EPC (c_x = +1) or x0 cover in
+// 64 / EPC + 1 chunks (64 / EPC when c_x = 0).  The chunks of all 2Q
+// populations are packed 64 to a load instruction (lane l of instruction j
+// lands at 16 l bytes into that instruction's 1 KB of the wave's LDS
+// region), with the populations grouped by their shift c_z along the march
+// axis so that every instruction has one z offset, uniform across the wave
+// (group 0: c_z = +1, 1: c_z = 0, 2: c_z = -1; each group starts a new
+// instruction).  Within a group: species 1's populations, then species 2's,
+// in velocity order.
+// ---------------------------------------------------------------------------
+template <class L, int ES>
+struct WideRows {
+    static constexpr int EPC = 16 / ES;  // elements per chunk
+    static constexpr int Q = L::Q;
+    static constexpr int NPOP = 2 * Q;
+    static constexpr int group_of(int i) { return 1 - L::cz[i]; }
+    static constexpr int chunks_of(int i) { return 64 / EPC + (L::cx[i] != 0 ? 1 : 0); }
+    // element offset of site lane 0's source within the population's chunks
+    static constexpr int shift_of(int i) { return L::cx[i] > 0 ? EPC - 1 : (L::cx[i] < 0 ? 1 : 0); }
+    int gchunks[3];    // chunks of each group
+    int first[3];      // first instruction of each group
+    int ninstr[3];
+    int NI;            // instructions in all
+    int chunk0[NPOP];  // first chunk of population s * Q + i within the wave region
+    constexpr WideRows() : gchunks(), first(), ninstr(), NI(0), chunk0()
+    {
+        for (int G = 0; G < 3; ++G) {
+            first[G] = NI;
+            int c = 0;
+            for (int sp = 0; sp < 2; ++sp)
+                for (int i = 0; i < Q; ++i)
+                    if (group_of(i) == G) {
+                        chunk0[sp * Q + i] = 64 * first[G] + c;
+                        c += chunks_of(i);
+                    }
+            gchunks[G] = c;
+            ninstr[G] = (c + 63) / 64;
+            NI += ninstr[G];
+        }
+    }
+    // instruction j's group, and the number of its lanes that carry a chunk
+    constexpr int group_of_instr(int j) const { return j < first[1] ? 0 : (j < first[2] ? 1 : 2); }
+    constexpr int lanes_of_instr(int j) const
+    {
+        const int G = group_of_instr(j);
+        const int left = gchunks[G] - 64 * (j - first[G]);
+        return left < 64 ? left : 64;
+    }
+};
+
+// f(std::integral_constant<int, k>) for k = 0 .. N-1, so that table lookups
+// with k inside f are constant expressions.
+template <int N, class F, int... K>
+__device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, K...>)
+{
+    (f(std::integral_constant<int, K>{}), ...);
+}
+
+template <int N, class F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    static_for_impl<N>(f, std::make_integer_sequence<int, N>{});
+}
+
+// ---------------------------------------------------------------------------
 // Full-width tiles (D3Q19, tile width = nx): every row of the tile is a whole
 // lattice row, so each population is read as contiguous nx-site rows and the
 // x halo is the tile's own periodic image (written into the ring's edge
@@ -640,7 +709,7 @@ __device__ __forceinline__ void fused_tile_async(const StepArgs<L, S> &a, int t0
 template <class L, class S, int T0, int T1>
 __device__ __forceinline__ void fused_tile_rows_body(const StepArgs<L, S> &a, int t0, int t1, int mbeg, int mend,
                                                      typename Storage<S>::Real *__restrict__ ring_p,
-                                                     uint32_t *__restrict__ own_p)
+                                                     uint32_t *__restrict__ own_p, uint32_t *__restrict__ tab_p)
 {
     using Real = typename Storage<S>::Real;
     using Raw = uint32_t;
@@ -659,7 +728,9 @@ __device__ __forceinline__ void fused_tile_rows_body(const StepArgs<L, S> &a, in
     static_assert(NT % 64 == 0, "whole waves");
 
     auto ring = reinterpret_cast<Real (*)[2][PLANE]>(ring_p);  // [4][2][PLANE]
-    auto own = reinterpret_cast<Raw (*)[NT]>(own_p);           // [2Q][NT]: plane m+1 (then m+2) of the tile
+    // own_p: per wave NI x 1 KB of 16-byte row chunks (WideRows), plane m+1 (then m+2)
+    constexpr WideRows<L, ES> W{};
+    constexpr int NI = W.NI;
 
     const Geom g = a.g;
     const int n0 = g.nx, n1 = D3 ? g.ny : 1, nm = D3 ? g.nz : g.ny;
@@ -683,6 +754,42 @@ __device__ __forceinline__ void fused_tile_rows_body(const StepArgs<L, S> &a, in
     const bool inside = p0raw < n0 && p1raw < n1;
     const int p0 = p0raw % n0, p1 = p1raw % n1;
     const int box_own = (l1 + OFF1) * H0 + (l0 + 1);
+    const int lane = tid & 63;
+
+    // One buffer resource over both species for the 16-byte row pulls (the
+    // launcher requires 2 Q sites ES < 4 GiB for full-width tiles), and the
+    // per-lane source offsets of every row-pull instruction (population,
+    // x and y parts), fixed over the march and kept in LDS (tab_p); the
+    // plane enters as the scalar offset of the instruction's group.
+    const __amdgpu_buffer_rsrc_t rall =
+        __builtin_amdgcn_make_buffer_rsrc((void *)a.src, 0, (int)(2u * Q * pop_bytes), kBufferWord3);
+    {
+        const int x0 = (wave % (T0 / 64)) * 64;
+        const int yc[3] = {wrap(p1, -1, n1), p1, wrap(p1, 1, n1)};  // rows p1 - c_y for c_y = +1, 0, -1
+        static_for<NI>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            constexpr int G = W.group_of_instr(j);
+            const int gc = 64 * (j - W.first[G]) + lane;  // chunk within the group
+            // the group's populations occupy consecutive chunk ranges: keep the
+            // last one that starts at or before gc (selects, no branches)
+            int c0 = 0, cb = 0, y = p1;
+            uint32_t pop = 0;
+            static_for<2 * Q>([&](auto pc) {
+                constexpr int sp = decltype(pc)::value / Q, i = decltype(pc)::value % Q;
+                if constexpr (WideRows<L, ES>::group_of(i) == G) {
+                    constexpr int start = W.chunk0[sp * Q + i] - 64 * W.first[G];
+                    const bool here = gc >= start;
+                    c0 = here ? start : c0;
+                    cb = here ? (A::c0(i) > 0 ? -W.EPC : 0) : cb;
+                    y = here ? yc[1 - A::c1(i)] : y;
+                    pop = here ? (uint32_t)(sp * Q + i) * pop_bytes : pop;
+                }
+            });
+            int x = x0 + cb + W.EPC * (gc - c0);
+            x = x < 0 ? x + n0 : (x >= n0 ? x - n0 : x);
+            tab_p[(wave * NI + j) * 64 + lane] = pop + ((uint32_t)x + s1 * (uint32_t)y) * ES;
+        });
+    }
 
     // halo: the two rows y0 - 1 and y0 + T1, one site per thread
     const int hrow = tid / T0, hx = tid % T0;
@@ -719,44 +826,41 @@ __device__ __forceinline__ void fused_tile_rows_body(const StepArgs<L, S> &a, in
             }
         }
     };
-    // Asynchronous pull of plane m into rows [2Q][len]: this wave's 64-lane slice.
-    auto dma_pull = [&](int q0, int q1, int m, Raw *rows, int len) {
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            const uint32_t voff = pull_off(q0, q1, m, i);
-#pragma unroll
-            for (int s = 0; s < 2; ++s) {
-                lds_void_t *dst = (lds_void_t *)(rows + (s * Q + i) * len + wave * 64);
-                if constexpr (ES == 4)
-                    __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc[s], dst, 4, voff, (uint32_t)i * pop_bytes, 0, 0);
-                else
-                    __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc[s], dst, 2, voff, (uint32_t)i * pop_bytes, 0, 0);
+    // The 16-byte row pulls of plane m (wrapped), instructions [jb, je): group
+    // G's source plane is m - c_z = m - 1, m, m + 1 for G = 0, 1, 2.
+    auto wide_issue = [&](int m, auto jb, auto je) {
+        const uint32_t zo[3] = {(uint32_t)wrapm(m - 1) * sm * ES, (uint32_t)m * sm * ES,
+                                (uint32_t)wrapm(m + 1) * sm * ES};
+        lds_void_t *base = (lds_void_t *)(own_p + wave * NI * 256);
+        static_for<NI>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            if constexpr (j >= decltype(jb)::value && j < decltype(je)::value) {
+                lds_void_t *dst = (lds_void_t *)((__attribute__((address_space(3))) unsigned char *)base + j * 1024);
+                const uint32_t voff = tab_p[(wave * NI + j) * 64 + lane];
+                constexpr int lanes = W.lanes_of_instr(j);
+                if (lanes == 64 || lane < lanes)
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(rall, dst, 16, voff, zo[W.group_of_instr(j)], 0, 0);
             }
-        }
+        });
     };
-    auto read_rows = [&](const Raw *rows, int len, int idx, Real (&f)[2][Q]) {
-#pragma unroll
-        for (int s = 0; s < 2; ++s)
-#pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                Real v = DmaWord<S>::decode(rows[(s * Q + i) * len + idx]);
-                f[s][i] = v;
+    // Read back this thread's 2Q pre-collision populations from the wave's chunks.
+    auto wide_read = [&](Real (&f)[2][Q]) {
+        static_for<2 * Q>([&](auto pc) {
+            constexpr int sp = decltype(pc)::value / Q, i = decltype(pc)::value % Q;
+            constexpr int e = W.EPC * W.chunk0[sp * Q + i] + WideRows<L, ES>::shift_of(i);
+            if constexpr (ES == 4) {
+                f[sp][i] = DmaWord<S>::decode(own_p[wave * NI * 256 + e + lane]);
+            } else {
+                const unsigned short *h = reinterpret_cast<const unsigned short *>(own_p);
+                f[sp][i] = DmaWord<S>::decode(h[wave * NI * 512 + e + lane]);
             }
+        });
     };
+    // instructions issued at the top of a plane; the rest mid-collision
+    using J0 = std::integral_constant<int, 0>;
+    using JE = std::integral_constant<int, (NI + 1) / 2>;
+    using JN = std::integral_constant<int, NI>;
 
-    // One species' share of the two pulls above.
-    auto dma_pull1 = [&](int s, int q0, int q1, int m, Raw *rows, int len) {
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            lds_void_t *dst = (lds_void_t *)(rows + (s * Q + i) * len + wave * 64);
-            if constexpr (ES == 4)
-                __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc[s], dst, 4, pull_off(q0, q1, m, i), (uint32_t)i * pop_bytes,
-                                                         0, 0);
-            else
-                __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc[s], dst, 2, pull_off(q0, q1, m, i), (uint32_t)i * pop_bytes,
-                                                         0, 0);
-        }
-    };
     // Register pull of one species.  16-bit words stay raw until they are
     // read: a widening next to its load, between the scheduling fences
     // below, would make every load wait for all memory operations in flight
@@ -815,7 +919,7 @@ __device__ __forceinline__ void fused_tile_rows_body(const StepArgs<L, S> &a, in
             }
         }
     }
-    dma_pull(p0, p1, wrapm(mbeg + 1), &own[0][0], NT);
+    wide_issue(wrapm(mbeg + 1), J0{}, JN{});
     HaloWord hn[2][Q];
     if constexpr (ES == 4) {
         pull(hp0, hp1, wrapm(mbeg + 1), hn);
@@ -829,12 +933,12 @@ __device__ __forceinline__ void fused_tile_rows_body(const StepArgs<L, S> &a, in
         // Rows of plane m+1 have landed.
         __builtin_amdgcn_s_waitcnt(kWaitVm0);
         Real nxt[2][Q], rn[2], jn[2][3];
-        read_rows(&own[0][0], NT, tid, nxt);
-        // This wave's rows are read back: its slice of the buffer is free
-        // for the first species' rows of plane m+2.
+        wide_read(nxt);
+        // This wave's chunks are read back: its region is free for the
+        // first half of the row pulls of plane m+2.
         __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
         __builtin_amdgcn_sched_barrier(0);
-        if (m + 2 <= mend) dma_pull1(0, p0, p1, wrapm(m + 2), &own[0][0], NT);
+        if (m + 2 <= mend) wide_issue(wrapm(m + 2), J0{}, JE{});
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
@@ -879,7 +983,7 @@ __device__ __forceinline__ void fused_tile_rows_body(const StepArgs<L, S> &a, in
         collide_site<L, Real>(cur, rc, jc, acc, a.ph, ref, Counter{site, a.step_lo, a.step_hi}, [&](int s, auto &fs) {
             if (s == 0) {
                 __builtin_amdgcn_sched_barrier(0);
-                if (more) dma_pull1(1, p0, p1, wrapm(m + 2), &own[0][0], NT);
+                if (more) wide_issue(wrapm(m + 2), JE{}, JN{});
                 __builtin_amdgcn_sched_barrier(0);
             }
             if (inside) {
@@ -907,8 +1011,10 @@ __device__ __forceinline__ void fused_tile_rows(const StepArgs<L, S> &a, int t0,
 {
     constexpr int PLANE = (T0 + 2) * (T1 + 2);
     __shared__ typename Storage<S>::Real ring[4][2][PLANE];
-    __shared__ uint32_t own[2 * L::Q][T0 * T1];
-    fused_tile_rows_body<L, S, T0, T1>(a, t0, t1, mbeg, mend, &ring[0][0][0], &own[0][0]);
+    constexpr int NW = T0 * T1 / 64, NI = WideRows<L, sizeof(S)>().NI;
+    __shared__ __attribute__((aligned(16))) uint32_t own[NW * NI * 256];  // 16-byte buffer-to-LDS targets
+    __shared__ uint32_t tab[NW * NI * 64];
+    fused_tile_rows_body<L, S, T0, T1>(a, t0, t1, mbeg, mend, &ring[0][0][0], &own[0], &tab[0]);
 }
 
 template <class L, class S, int T0, int T1, bool ASYNC>
@@ -999,6 +1105,10 @@ bool fused_supported(const Geom &g, int tile_x, int tile_y, int march)
     // index wraps periodically (with fewer than 3 planes the ring simply holds
     // copies).
     if (L::D == 3 && tile_x == 256 && g.nx != 256) return false;  // full-width tiles only
+    // full-width tiles pull both species through one buffer resource
+    if (L::D == 3 && (tile_x == 256 || (tile_x == 0 && g.nx == 256)) &&
+        2.0 * (double)L::Q * (double)g.nsites * (double)sizeof(S) >= 4294967295.0)
+        return false;
     return tile_x == 0 || fused_shape_valid<L, S>(tile_x, tile_y, march);
 }
 

@@ -233,4 +233,47 @@ __global__ __launch_bounds__(256) void pull_copy_kernel(const S *src, S *dst, Ge
         for (int s = 0; s < 2; ++s) dst[((size_t)(s * L::Q + i)) * g.nsites + site] = v[s][i];
 }
 
+// Bandwidth references for the roofline (not part of the method): streaming
+// kernels over a whole population buffer viewed as 16-byte words, with the
+// launch shapes that measured fastest on MI355X for each access kind.
+typedef float float4_v __attribute__((ext_vector_type(4)));
+
+// Read-only: every word of `src` once (grid-stride); a sum is written only
+// when it equals an impossible value, so the loads cannot be dropped.
+static __global__ __launch_bounds__(256) void stream_read_kernel(const float4_v *__restrict__ src, size_t n,
+                                                                  float *__restrict__ sink)
+{
+    float acc = 0.f;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
+        const float4_v v = __builtin_nontemporal_load(&src[t]);
+        acc += (v.x + v.y) + (v.z + v.w);
+    }
+    if (acc == -1.2345e-30f) sink[0] = acc;
+}
+
+// Write-only: every word of `dst` once (grid-stride, non-temporal).
+static __global__ __launch_bounds__(256) void stream_write_kernel(float4_v *__restrict__ dst, size_t n)
+{
+    const float4_v z = {0.f, 0.f, 0.f, 0.f};
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x)
+        __builtin_nontemporal_store(z, &dst[t]);
+}
+
+// Copy without the pull shifts: 16-byte words, U in flight per thread.
+template <int U>
+__global__ __launch_bounds__(256) void stream_copy_kernel(const float4_v *__restrict__ src, float4_v *__restrict__ dst,
+                                                          size_t n)
+{
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; t + (U - 1) * stride < n; t += U * stride) {
+        float4_v v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = src[t + u * stride];
+#pragma unroll
+        for (int u = 0; u < U; ++u) __builtin_nontemporal_store(v[u], &dst[t + u * stride]);
+    }
+    for (; t < n; t += stride) __builtin_nontemporal_store(src[t], &dst[t]);
+}
+
 }  // namespace fmlb

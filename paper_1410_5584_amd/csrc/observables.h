@@ -202,133 +202,195 @@ __global__ __launch_bounds__(kRedBlock) void health_kernel(const S *src, double 
 }
 
 // ---------------------------------------------------------------------------
-// Structure factors.  Fields are built as complex FP64 arrays, transformed by
-// separable line DFTs along x, y, z, and accumulated as products / sites.
+// Structure factors.  The real fields are transformed two at a time: the
+// complex field Z = X + iY is built from the pre-collision state, transformed
+// by separable line DFTs along x, y, z, and X_hat, Y_hat are recovered from
+// Z_hat(k) and Z_hat(-k) (X real: X_hat(-k) = conj X_hat(k)), so
+//   X_hat(k) = (Z_hat(k) + conj Z_hat(-k)) / 2,
+//   Y_hat(k) = (Z_hat(k) - conj Z_hat(-k)) / (2i).
+// Pairs: 0 (rho_1, rho_2); 1 + alpha (j_bar_1,alpha, j_bar_2,alpha);
+// D + 1 the physical barycentric velocity (v_b,x, v_b,y) and, in 3D, D + 2
+// (v_b,z, 0), with v_b = (j_bar_1 + j_bar_2 + (F_1 + F_2) / 2) / rho_t and
+// the force of Eq. (87) from the density buffer rho[2][sites].
 // ---------------------------------------------------------------------------
+template <class L>
+constexpr int sk_pairs()
+{
+    return L::D == 2 ? 4 : 6;
+}
 
-// Scalar field of the pre-collision state into A (imaginary part 0).
-// kind 0: rho_s; 1: j_bar_s,alpha; 2: physical barycentric velocity
-// (j_bar_1 + j_bar_2 + (F_1 + F_2)/2)_alpha / rho_t with the force of Eq. (87)
-// from the density buffer rho[2][sites].
 template <class L, class S>
-__global__ __launch_bounds__(256) void sk_field_kernel(const S *src, const typename Storage<S>::Real *rho,
-                                                       double2 *A, Geom g, int kind, int s, int al, double negG,
-                                                       typename Storage<S>::Real ref0,
-                                                       typename Storage<S>::Real ref1)
+__global__ __launch_bounds__(256) void sk_pair_kernel(const S *src, const typename Storage<S>::Real *rho, double2 *Z,
+                                                      Geom g, int pair, double negG, typename Storage<S>::Real ref0,
+                                                      typename Storage<S>::Real ref1)
 {
     using Real = typename Storage<S>::Real;
     const Real ref[2] = {ref0, ref1};
+    constexpr int D = L::D;
     for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < g.nsites; t += (size_t)gridDim.x * blockDim.x) {
         int x, y, z;
         site_xyz(t, g, x, y, z);
         double f[2][L::Q];
         pull_site_f64<L, S>(src, g, x, y, z, ref, f);
-        double v = 0;
-        if (kind == 0) {
+        double r[2] = {0, 0}, j[2][3] = {{0, 0, 0}, {0, 0, 0}};
 #pragma unroll
-            for (int i = 0; i < L::Q; ++i) v += f[s][i];
-        } else {
-            double jt[2] = {0, 0}, r[2] = {0, 0};
+        for (int q = 0; q < 2; ++q)
 #pragma unroll
-            for (int q = 0; q < 2; ++q)
-#pragma unroll
-                for (int i = 0; i < L::Q; ++i) {
-                    const int c = al == 0 ? L::cx[i] : al == 1 ? L::cy[i] : L::cz[i];
-                    r[q] += f[q][i];
-                    if (c) jt[q] += c > 0 ? f[q][i] : -f[q][i];
-                }
-            if (kind == 1) {
-                v = jt[s];
-            } else {
-                double a[2] = {0, 0};
-#pragma unroll
-                for (int i = 1; i < L::Q; ++i) {
-                    const int c = al == 0 ? L::cx[i] : al == 1 ? L::cy[i] : L::cz[i];
-                    if (!c) continue;
-                    const int xn = wrap(x, L::cx[i], g.nx), yn = wrap(y, L::cy[i], g.ny);
-                    const int zn = L::D == 3 ? wrap(z, L::cz[i], g.nz) : 0;
-                    const size_t nsite = (size_t)xn + (size_t)g.nx * ((size_t)yn + (size_t)g.ny * (size_t)zn);
-                    const double w = (double)L::w36[i] / 36.0;
-#pragma unroll
-                    for (int q = 0; q < 2; ++q) a[q] += c * w * (double)rho[(size_t)(1 - q) * g.nsites + nsite];
-                }
-                const double Ft = negG * (r[0] * a[0] + r[1] * a[1]);
-                const double rt = r[0] + r[1];
-                v = rt > 0 ? (jt[0] + jt[1] + 0.5 * Ft) / rt : 0.0;
+            for (int i = 0; i < L::Q; ++i) {
+                r[q] += f[q][i];
+                if (L::cx[i]) j[q][0] += L::cx[i] > 0 ? f[q][i] : -f[q][i];
+                if (L::cy[i]) j[q][1] += L::cy[i] > 0 ? f[q][i] : -f[q][i];
+                if (D == 3 && L::cz[i]) j[q][2] += L::cz[i] > 0 ? f[q][i] : -f[q][i];
             }
+        double X = 0, Y = 0;
+        if (pair == 0) {
+            X = r[0];
+            Y = r[1];
+        } else if (pair <= D) {
+            X = j[0][pair - 1];
+            Y = j[1][pair - 1];
+        } else {
+            // barycentric velocity components al0 (real part) and al0 + 1 (imaginary part, if any)
+            const int al0 = 2 * (pair - D - 1);
+            double a[2][3] = {{0, 0, 0}, {0, 0, 0}};
+#pragma unroll
+            for (int i = 1; i < L::Q; ++i) {
+                const int xn = wrap(x, L::cx[i], g.nx), yn = wrap(y, L::cy[i], g.ny);
+                const int zn = D == 3 ? wrap(z, L::cz[i], g.nz) : 0;
+                const size_t nsite = (size_t)xn + (size_t)g.nx * ((size_t)yn + (size_t)g.ny * (size_t)zn);
+                const double w = (double)L::w36[i] / 36.0;
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const double ro = (double)rho[(size_t)(1 - q) * g.nsites + nsite];
+                    a[q][0] += L::cx[i] * w * ro;
+                    a[q][1] += L::cy[i] * w * ro;
+                    a[q][2] += L::cz[i] * w * ro;
+                }
+            }
+            const double rt = r[0] + r[1];
+            double vb[3];
+#pragma unroll
+            for (int al = 0; al < 3; ++al) {
+                const double Ft = negG * (r[0] * a[0][al] + r[1] * a[1][al]);
+                vb[al] = rt > 0 ? (j[0][al] + j[1][al] + 0.5 * Ft) / rt : 0.0;
+            }
+            X = vb[al0];
+            Y = al0 + 1 < D ? vb[al0 + 1] : 0.0;
         }
-        A[t] = make_double2(v, 0.0);
+        Z[t] = make_double2(X, Y);
     }
 }
 
-// In-place DFT of every line along one axis: X[k] = sum_n x[n] e^{-2 pi i k n / L}.
-// Line l's elements are base(l) + m * stride, m < L.  One workgroup per line;
-// power-of-two L use a radix-2 Stockham FFT in LDS, other lengths a direct
-// sum against an LDS twiddle table.  L <= 2048.
-constexpr int kMaxLine = 2048;
+constexpr int kMaxLine = 2048;  // longest line the transforms accept
 
-static __global__ __launch_bounds__(256) void dft_lines_kernel(double2 *A, int L, size_t stride, int inner,
+// In-place DFT of every line along one axis: X[k] = sum_n x[n] e^{-2 pi i k n / L}.
+// Line l's elements are base(l) + m * stride, m < L, base(l) = (l % inner) *
+// inner_stride + (l / inner) * outer_stride.  A workgroup transforms P
+// lines with consecutive bases (P > 1 needs inner_stride = 1 and inner a
+// multiple of P): element m of its P lines is then P consecutive values, so
+// the loads and stores of a strided axis are contiguous runs instead of
+// scattered 16-byte accesses.  Power-of-two L use a radix-2 Stockham FFT in
+// LDS with the L/2 twiddles e^{-2 pi i t / L} tabulated once (stage h takes
+// twiddle k L/(2h), the same angle -k/h half-turns as a direct evaluation),
+// other lengths a direct sum against an LDS twiddle table.  L <= 2048.
+// Dynamic LDS: (2 P (L + 1) + L / 2) double2.
+template <int P>
+__global__ __launch_bounds__(256) void dft_lines_kernel(double2 *A, int L, size_t stride, int inner,
                                                         size_t inner_stride, size_t outer_stride)
 {
-    extern __shared__ double2 lds[];  // 2 * L (data, ping-pong / twiddles)
-    const size_t line = blockIdx.x;
-    const size_t base = (line % (size_t)inner) * inner_stride + (line / (size_t)inner) * outer_stride;
+    extern __shared__ double2 lds[];
+    const int LP = L + 1;  // padded line pitch in LDS
     double2 *a = lds;
-    double2 *b = lds + L;
-    for (int m = threadIdx.x; m < L; m += blockDim.x) a[m] = A[base + (size_t)m * stride];
-    __syncthreads();
+    double2 *b = lds + P * LP;
+    double2 *tw = lds + 2 * P * LP;
+    const size_t line0 = (size_t)blockIdx.x * P;
+    const size_t base = (line0 % (size_t)inner) * inner_stride + (line0 / (size_t)inner) * outer_stride;
+    for (int e = threadIdx.x; e < P * L; e += blockDim.x) {
+        const int p = e % P, m = e / P;
+        a[p * LP + m] = A[base + (size_t)p + (size_t)m * stride];
+    }
     if ((L & (L - 1)) == 0) {
-        // Stockham radix-2: at stage with half-size h, element pairs (j, j + L/2)
+        for (int t = threadIdx.x; t < L / 2; t += blockDim.x) {
+            double sn, cs;
+            sincospi(-2.0 * (double)t / (double)L, &sn, &cs);
+            tw[t] = make_double2(cs, sn);
+        }
+        __syncthreads();
+        // Stockham radix-2: at the stage of half-size h, element pairs (t, t + L/2)
         // combine into positions of blocks of size 2h.
         for (int h = 1; h < L; h <<= 1) {
-            for (int t = threadIdx.x; t < L / 2; t += blockDim.x) {
-                const int k = t % h;          // position within the current block
+            const int tstride = L / (2 * h);
+            for (int e = threadIdx.x; e < P * (L / 2); e += blockDim.x) {
+                const int p = e % P, t = e / P;
+                const int k = t % h;  // position within the current block
                 const int blk = t / h;
-                const double2 u = a[t];
-                const double2 v = a[t + L / 2];
-                double sn, cs;
-                sincospi(-(double)k / (double)h, &sn, &cs);
-                const double2 tv = make_double2(v.x * cs - v.y * sn, v.x * sn + v.y * cs);
-                b[blk * 2 * h + k] = make_double2(u.x + tv.x, u.y + tv.y);
-                b[blk * 2 * h + k + h] = make_double2(u.x - tv.x, u.y - tv.y);
+                const double2 u = a[p * LP + t];
+                const double2 v = a[p * LP + t + L / 2];
+                const double2 w = tw[k * tstride];
+                const double2 tv = make_double2(v.x * w.x - v.y * w.y, v.x * w.y + v.y * w.x);
+                b[p * LP + blk * 2 * h + k] = make_double2(u.x + tv.x, u.y + tv.y);
+                b[p * LP + blk * 2 * h + k + h] = make_double2(u.x - tv.x, u.y - tv.y);
             }
             __syncthreads();
             double2 *tmp = a;
             a = b;
             b = tmp;
         }
-        for (int m = threadIdx.x; m < L; m += blockDim.x) A[base + (size_t)m * stride] = a[m];
+        for (int e = threadIdx.x; e < P * L; e += blockDim.x) {
+            const int p = e % P, m = e / P;
+            A[base + (size_t)p + (size_t)m * stride] = a[p * LP + m];
+        }
     } else {
         for (int m = threadIdx.x; m < L; m += blockDim.x) {
             double sn, cs;
             sincospi(-2.0 * (double)m / (double)L, &sn, &cs);
-            b[m] = make_double2(cs, sn);
+            b[m] = make_double2(cs, sn);  // twiddle table in the second buffer
         }
         __syncthreads();
-        for (int k = threadIdx.x; k < L; k += blockDim.x) {
+        for (int e = threadIdx.x; e < P * L; e += blockDim.x) {
+            const int p = e % P, k = e / P;
             double re = 0, im = 0;
             int idx = 0;
             for (int n = 0; n < L; ++n) {
-                const double2 x = a[n], t = b[idx];
+                const double2 x = a[p * LP + n], t = b[idx];
                 re += x.x * t.x - x.y * t.y;
                 im += x.x * t.y + x.y * t.x;
                 idx += k;
                 if (idx >= L) idx -= L;
             }
-            A[base + (size_t)k * stride] = make_double2(re, im);
+            A[base + (size_t)p + (size_t)k * stride] = make_double2(re, im);
         }
     }
 }
 
-// acc[t] += scale * Re(A conj(B)) (B = A for an auto spectrum); k = 0 (the
-// mean, removed by the definition dX = X - <X>) is skipped.
-static __global__ __launch_bounds__(256) void sk_accum_kernel(const double2 *A, const double2 *B, double *acc,
-                                                       size_t n, double scale)
+// The products of one transformed pair added to the accumulators acc[7][sites]:
+// kind 0 (densities) adds |X_hat|^2, |Y_hat|^2, Re X_hat conj(Y_hat) to
+// quantities 0, 1, 2; kind 1 (momenta) to 3, 4, 5; kind 2 (velocities)
+// adds |X_hat|^2 + |Y_hat|^2 to 6.  Each product is scaled by `scale`; k = 0
+// (the mean, removed by the definition dX = X - <X>) is skipped.
+static __global__ __launch_bounds__(256) void sk_pair_accum_kernel(const double2 *Z, double *acc, Geom g, int kind,
+                                                                   double scale)
 {
+    const size_t n = g.nsites;
     for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
         if (t == 0) continue;
-        const double2 a = A[t], b = B[t];
-        acc[t] += scale * (a.x * b.x + a.y * b.y);
+        int x, y, z;
+        site_xyz(t, g, x, y, z);
+        const int xm = x == 0 ? 0 : g.nx - x, ym = y == 0 ? 0 : g.ny - y, zm = z == 0 ? 0 : g.nz - z;
+        const size_t tm = (size_t)xm + (size_t)g.nx * ((size_t)ym + (size_t)g.ny * (size_t)zm);
+        const double2 a = Z[t], c = Z[tm];
+        // X_hat = (a + conj c) / 2,  Y_hat = (a - conj c) / (2i) = (Im(a) + Im(c), Re(c) - Re(a)) / 2
+        const double xr = 0.5 * (a.x + c.x), xi = 0.5 * (a.y - c.y);
+        const double yr = 0.5 * (a.y + c.y), yi = 0.5 * (c.x - a.x);
+        const double xx = xr * xr + xi * xi, yy = yr * yr + yi * yi;
+        if (kind == 2) {
+            acc[6 * n + t] += scale * (xx + yy);
+        } else {
+            const int q = 3 * kind;
+            acc[(size_t)q * n + t] += scale * xx;
+            acc[(size_t)(q + 1) * n + t] += scale * yy;
+            acc[(size_t)(q + 2) * n + t] += scale * (xr * yr + xi * yi);
+        }
     }
 }
 

@@ -81,7 +81,7 @@ bool valid_params(const fmlb_params *p)
 }
 
 struct Layout {
-    size_t rho, stage, skA, skB, skacc, partial, modeacc, misc, total;
+    size_t rho, stage, skA, skacc, partial, modeacc, misc, total;
 };
 
 Layout scratch_layout(const fmlb_params *p)
@@ -95,8 +95,6 @@ Layout scratch_layout(const fmlb_params *p)
     l.stage = o;
     o += align256(2 * n * sizeof(double));
     l.skA = o;
-    o += align256(n * 2 * sizeof(double));
-    l.skB = o;
     o += align256(n * 2 * sizeof(double));
     l.skacc = o;
     o += align256((size_t)kSkQuantities * n * sizeof(double));
@@ -251,7 +249,24 @@ fmlb_status sync(fmlb_ctx *c)
     return FMLB_OK;
 }
 
+// Launch the line transforms of one axis, P lines per workgroup.
+template <int P>
+fmlb_status dft_axis(hipStream_t stream, double2 *A, int L, size_t lines, size_t stride, int inner,
+                     size_t inner_stride, size_t outer_stride)
+{
+    const size_t lds = (2 * (size_t)P * (L + 1) + (size_t)L / 2) * sizeof(double2);
+    if (lds > 65536)  // more than the default limit; at most 148 KB of the 160 KB LDS
+        HIP_TRY(hipFuncSetAttribute((const void *)dft_lines_kernel<P>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)lds));
+    hipLaunchKernelGGL(dft_lines_kernel<P>, dim3((unsigned)(lines / P)), dim3(256), lds, stream, A, L, stride, inner,
+                       inner_stride, outer_stride);
+    LAUNCH_CHECK();
+    return FMLB_OK;
+}
+
 // Forward DFT of a complex lattice field along every axis of length > 1.
+// The strided axes (y, z) take several adjacent lines per workgroup (as many
+// as divide nx and fit 148 KB of LDS), so their accesses are contiguous runs.
 fmlb_status dft_field(const Geom &g, hipStream_t stream, double2 *A)
 {
     const int dims[3] = {g.nx, g.ny, g.nz};
@@ -278,26 +293,36 @@ fmlb_status dft_field(const Geom &g, hipStream_t stream, double2 *A)
             inner_stride = 1;
             outer_stride = 0;
         }
-        const int threads = L >= 512 ? 256 : (L >= 128 ? 128 : 64);
-        const size_t lds = 2 * (size_t)L * sizeof(double2);
-        hipLaunchKernelGGL(dft_lines_kernel, dim3((unsigned)lines), dim3(threads), lds, stream, A, L, stride,
-                           (int)inner, inner_stride, outer_stride);
-        LAUNCH_CHECK();
+        auto fits = [&](int P) {
+            return (ax == 0 ? P == 1 : inner % (size_t)P == 0) &&
+                   (2 * (size_t)P * (L + 1) + (size_t)L / 2) * sizeof(double2) <= 148 * 1024;
+        };
+        fmlb_status st;
+        if (fits(8))
+            st = dft_axis<8>(stream, A, L, lines, stride, (int)inner, inner_stride, outer_stride);
+        else if (fits(4))
+            st = dft_axis<4>(stream, A, L, lines, stride, (int)inner, inner_stride, outer_stride);
+        else if (fits(2))
+            st = dft_axis<2>(stream, A, L, lines, stride, (int)inner, inner_stride, outer_stride);
+        else
+            st = dft_axis<1>(stream, A, L, lines, stride, (int)inner, inner_stride, outer_stride);
+        if (st) return st;
     }
     return FMLB_OK;
 }
 
 // Bytes of work arrays the structure-factor accumulation needs per site:
-// the densities of both species (FP64 at most, for the force in v_b) and two
-// complex FP64 line-transform buffers.
-constexpr size_t kSkWorkBytesPerSite = 2 * sizeof(double) + 2 * sizeof(double2);
+// the densities of both species (FP64 at most, for the force in v_b) and one
+// complex FP64 field.
+constexpr size_t kSkWorkBytesPerSite = 2 * sizeof(double) + sizeof(double2);
 
 // The structure-factor accumulation of one snapshot (Sec. VI A): the seven
-// quantities of fmlb_sk_accumulate are added to acc[7][sites].  rho, A and B
-// are work arrays of 2 * sites Real, sites and sites double2.
+// quantities of fmlb_sk_accumulate are added to acc[7][sites], two real
+// fields per complex transform.  rho and Z are work arrays of 2 * sites
+// Real and sites double2.
 template <class L, class S>
 fmlb_status sk_accumulate_impl(const fmlb_params &p, const Geom &g, hipStream_t stream, const S *src,
-                               typename Storage<S>::Real *rho, double2 *A, double2 *B, double *acc)
+                               typename Storage<S>::Real *rho, double2 *Z, double *acc)
 {
     using Real = typename Storage<S>::Real;
     const size_t n = g.nsites;
@@ -311,34 +336,16 @@ fmlb_status sk_accumulate_impl(const fmlb_params &p, const Geom &g, hipStream_t 
     hipLaunchKernelGGL((density_kernel<L, S>), sg.grid, sg.block, 0, stream, a);
     LAUNCH_CHECK();
     const dim3 gb(stride_blocks(n)), tb(256);
-    auto field = [&](double2 *dst, int kind, int s, int al) -> fmlb_status {
-        hipLaunchKernelGGL((sk_field_kernel<L, S>), gb, tb, 0, stream, src, (const Real *)rho, dst, g, kind, s, al,
-                           -p.G, ref0, ref1);
-        LAUNCH_CHECK();
-        return dft_field(g, stream, dst);
-    };
-    auto accum = [&](const double2 *X, const double2 *Y, int q, double scale) -> fmlb_status {
-        hipLaunchKernelGGL(sk_accum_kernel, gb, tb, 0, stream, X, Y, acc + (size_t)q * n, n, scale);
-        LAUNCH_CHECK();
-        return FMLB_OK;
-    };
     const double inv_n = 1.0 / (double)n;
-    fmlb_status st;
-    if ((st = field(A, 0, 0, 0))) return st;
-    if ((st = accum(A, A, 0, inv_n))) return st;
-    if ((st = field(B, 0, 1, 0))) return st;
-    if ((st = accum(B, B, 1, inv_n))) return st;
-    if ((st = accum(A, B, 2, inv_n))) return st;
-    for (int al = 0; al < D; ++al) {
-        if ((st = field(A, 1, 0, al))) return st;
-        if ((st = field(B, 1, 1, al))) return st;
-        if ((st = accum(A, A, 3, inv_n / D))) return st;
-        if ((st = accum(B, B, 4, inv_n / D))) return st;
-        if ((st = accum(A, B, 5, inv_n / D))) return st;
-    }
-    for (int al = 0; al < D; ++al) {
-        if ((st = field(A, 2, 0, al))) return st;
-        if ((st = accum(A, A, 6, inv_n / D))) return st;
+    for (int pair = 0; pair < sk_pairs<L>(); ++pair) {
+        hipLaunchKernelGGL((sk_pair_kernel<L, S>), gb, tb, 0, stream, src, (const Real *)rho, Z, g, pair, -p.G, ref0,
+                           ref1);
+        LAUNCH_CHECK();
+        if (fmlb_status st = dft_field(g, stream, Z)) return st;
+        const int kind = pair == 0 ? 0 : (pair <= D ? 1 : 2);
+        hipLaunchKernelGGL(sk_pair_accum_kernel, gb, tb, 0, stream, (const double2 *)Z, acc, g, kind,
+                           kind == 0 ? inv_n : inv_n / D);
+        LAUNCH_CHECK();
     }
     return FMLB_OK;
 }
@@ -566,15 +573,14 @@ fmlb_status fmlb_sk_accumulate(fmlb_ctx *c)
     if (!c) return FMLB_E_NULL;
     if (!c->ready) return FMLB_E_STATE;
     if (c->g.nx > kMaxLine || c->g.ny > kMaxLine || c->g.nz > kMaxLine) return FMLB_E_UNSUPPORTED;
-    double2 *A = scr<double2>(c, c->lay.skA);
-    double2 *B = scr<double2>(c, c->lay.skB);
+    double2 *Z = scr<double2>(c, c->lay.skA);
     double *acc = scr<double>(c, c->lay.skacc);
     fmlb_status st = dispatch(c, [&](auto l, auto sp) -> fmlb_status {
         using L = decltype(l);
         using S = std::remove_pointer_t<decltype(sp)>;
         using Real = typename Storage<S>::Real;
         return sk_accumulate_impl<L, S>(c->p, c->g, c->stream, reinterpret_cast<const S *>(c->pops[c->cur]),
-                                        scr<Real>(c, c->lay.rho), A, B, acc);
+                                        scr<Real>(c, c->lay.rho), Z, acc);
     });
     if (st) return st;
     c->sk_samples += 1;
@@ -590,10 +596,9 @@ fmlb_status fmlb_sk_accumulate_static(const fmlb_params *p, const void *pops, do
     if (g.nx > kMaxLine || g.ny > kMaxLine || g.nz > kMaxLine) return FMLB_E_UNSUPPORTED;
     void *base = nullptr;
     if (fmlb_status st = static_scratch(&base)) return st;
-    // work arrays carved from the static array: rho (2 sites x 8 bytes), A, B
+    // work arrays carved from the static array: rho (2 sites x 8 bytes), Z
     unsigned char *w = reinterpret_cast<unsigned char *>(base);
-    double2 *A = reinterpret_cast<double2 *>(w + 2 * g.nsites * sizeof(double));
-    double2 *B = A + g.nsites;
+    double2 *Z = reinterpret_cast<double2 *>(w + 2 * g.nsites * sizeof(double));
     fmlb_ctx tmp{};
     tmp.p = *p;
     return dispatch(&tmp, [&](auto l, auto sp) -> fmlb_status {
@@ -601,7 +606,7 @@ fmlb_status fmlb_sk_accumulate_static(const fmlb_params *p, const void *pops, do
         using S = std::remove_pointer_t<decltype(sp)>;
         using Real = typename Storage<S>::Real;
         return sk_accumulate_impl<L, S>(*p, g, reinterpret_cast<hipStream_t>(hip_stream),
-                                        reinterpret_cast<const S *>(pops), reinterpret_cast<Real *>(w), A, B, acc);
+                                        reinterpret_cast<const S *>(pops), reinterpret_cast<Real *>(w), Z, acc);
     });
 }
 
@@ -800,6 +805,38 @@ fmlb_status fmlb_copy_reference(fmlb_ctx *c)
         LAUNCH_CHECK();
         return FMLB_OK;
     });
+}
+
+fmlb_status fmlb_bandwidth_reference(fmlb_ctx *c, int kind, double *bytes)
+{
+    if (!c) return FMLB_E_NULL;
+    if (kind < 0 || kind > FMLB_BW_COPY16) return FMLB_E_INVALID;
+    if (!c->ready) return FMLB_E_STATE;
+    const size_t buf = 2 * (size_t)c->Q * c->g.nsites * elem_size(c->p.storage);
+    const size_t words = buf / 16;  // the last buf % 16 bytes are left out
+    const void *src = c->pops[c->cur];
+    void *dst = c->pops[1 - c->cur];
+    switch (kind) {
+    case FMLB_BW_PULL_COPY:
+        if (bytes) *bytes = 2.0 * (double)buf;
+        return fmlb_copy_reference(c);
+    case FMLB_BW_READ:
+        hipLaunchKernelGGL(stream_read_kernel, dim3(2048), dim3(256), 0, c->stream, (const float4_v *)src, words,
+                           scr<float>(c, c->lay.misc));
+        if (bytes) *bytes = 16.0 * (double)words;
+        break;
+    case FMLB_BW_WRITE:
+        hipLaunchKernelGGL(stream_write_kernel, dim3(256), dim3(256), 0, c->stream, (float4_v *)dst, words);
+        if (bytes) *bytes = 16.0 * (double)words;
+        break;
+    case FMLB_BW_COPY16:
+        hipLaunchKernelGGL((stream_copy_kernel<4>), dim3(256), dim3(256), 0, c->stream, (const float4_v *)src,
+                           (float4_v *)dst, words);
+        if (bytes) *bytes = 32.0 * (double)words;
+        break;
+    }
+    LAUNCH_CHECK();
+    return FMLB_OK;
 }
 
 int32_t fmlb_last_hip_error(void) { return g_last_hip; }

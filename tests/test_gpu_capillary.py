@@ -10,10 +10,11 @@ Here:
   - the Laplace experiment: droplets of several radii, with the bulk pressure of the model
     p = c_s^2 (rho_1 + rho_2) + c_s^2 G rho_1 rho_2 (the momentum balance of the pair force of
     Eq. (87) across an interface, sum_i w_i c_i c_i = c_s^2 I), gamma from dp = gamma / R;
-    it gives 0.151;
-  - the spectrum of both interfaces of the fluctuating stripe against Eq. (91) with the paper's
-    gamma = 0.174, which it follows within a few percent (so the spectrum's gamma agrees with the
-    paper's, and the Laplace value here is the one that differs);
+    it gives 0.149, close to the mechanical surface tension of a flat interface with the same
+    dense phase (the pair-force virial on the oracle's steady stripe: 0.155);
+  - the spectrum of both interfaces of the fluctuating stripe against Eq. (91), with the paper's
+    gamma = 0.174 (within a few per cent) and with the mechanical gamma of the same stripe
+    (0.161: about 10 % below the law);
   - FP32 against FP64 storage on the same spectrum.
 """
 import numpy as np
@@ -43,51 +44,80 @@ def _pressure(r1, r2):
     return CS2 * (r1 + r2) + CS2 * G * r1 * r2
 
 
-def _laplace_gamma(fm):
-    n = 128
+def _laplace_points(fm, n=256, radii=(20.0, 30.0, 45.0, 64.0), steps=40000):
+    """Droplets of species 1 in species 2 (k_BT = 0, FP64): per droplet the
+    equimolar radius (from the dense species' excess area), the bulk
+    pressure difference and the inside / outside densities."""
     y, x = np.mgrid[0:n, 0:n]
     pts = []
-    for R in (12.0, 16.0, 22.0, 30.0):
+    for R in radii:
         inside = (x - n / 2 + 0.5) ** 2 + (y - n / 2 + 0.5) ** 2 < R * R
         r1 = np.where(inside, DENSE, LIGHT)[None]
         r2 = np.where(inside, LIGHT, DENSE)[None]
         lat = fm.Lattice(fm.Params(lattice="d2q9", storage="f64", nx=n, ny=n, tau=(1.0, 1.0), tau_d=1.0, G=G,
                                    kT=0.0, seed=1))
         lat.init_density(r1, r2)
-        lat.step(20000)
+        lat.step(steps)
         rho = lat.moments()[0][:, 0]
         lat.close()
         rin = rho[:, n // 2, n // 2]
         rout = rho[:, 0, 0]
-        # radius from the area the dense species occupies above the outer value
         area = np.sum((rho[0] - rout[0]) / (rin[0] - rout[0]))
         Reff = np.sqrt(area / np.pi)
         dp = _pressure(*rin) - _pressure(*rout)
         pts.append((Reff, dp, rin, rout))
-        _say(f"  droplet R0 = {R}: R = {Reff:.3f}, inside {rin.round(4)}, outside {rout.round(4)}, dp = {dp:.5e}")
-    inv_r = np.array([1.0 / p[0] for p in pts])
-    dps = np.array([p[1] for p in pts])
-    gamma, c0 = np.polyfit(inv_r, dps, 1)
-    return gamma, c0, pts
+        _say(f"  droplet R0 = {R}: R = {Reff:.3f}, inside {rin.round(4)}, outside {rout.round(4)}, "
+             f"dp = {dp:.5e}, dp R = {dp * Reff:.4f}")
+    return pts
+
+
+def _mechanical_gamma(n=200, width=100, steps=40000):
+    """The oracle's flat G = 1.5 interface (periodic box of n sites, a stripe
+    of `width`): surface tension from the pair-force virial of Eq. (87),
+    gamma = (G / 2) sum_x sum_i w_i (c_ix^2 - c_iy^2) rho_1(x) rho_2(x + c_i)
+    per interface (two in the box), and the dense phase's density."""
+    import oracle
+    import workloads
+    r1, r2 = workloads.stripe_density(n, 1, width, DENSE, LIGHT)
+    s = oracle.Sim(oracle.Params(lattice=0, nx=n, ny=1, nz=1, tau=(1.0, 1.0), tau_d=1.0, G=G, kT=0.0))
+    s.init_density(r1, r2)
+    s.step(steps)
+    rho = s.moments()[0][:, 0, 0]
+    tot = sum(s.w[i] * (s.c[i, 0] ** 2 - s.c[i, 1] ** 2) * np.sum(rho[0] * np.roll(rho[1], -s.c[i, 0]))
+              for i in range(s.Q))
+    return G * tot / 2, float(rho[0, n // 2])
 
 
 def test_laplace_surface_tension(fm):
-    """gamma from dp = gamma / R over four droplets (equimolar radii from
-    the dense species' excess area).  Measured here: 0.151.  The paper
-    reports 0.174 from its own Laplace experiment without radii, radius
-    definition or fit, so the bound against it is loose (15 %); the
-    capillary spectrum below is the sharper check of gamma.  The fit's
-    intercept, a finite-size pressure offset, must be small against the
-    smallest droplet's dp."""
+    """Laplace's law dp = gamma / R (2D) for four droplets of equimolar radius
+    19.5 to 63.6 in a 256^2 box, fitted with an intercept.  Bounds from the
+    fit: the intercept within 3 standard errors of zero (no pressure offset),
+    and every droplet's dp R within the propagated fit error of gamma (the
+    law holds droplet by droplet).  Measured: gamma = 0.149 +- 0.001.
+    The mechanical surface tension of the oracle's flat interface whose
+    dense phase is closest to the droplets' (a 200-site box with a 100-site
+    stripe: 2.320 against 2.31-2.32) is 0.155: 4 % (5 fit errors) above the
+    Laplace value, a gap this test does not resolve (curvature corrections
+    and the droplets' own tie-lines); the two routes to the same quantity
+    are only checked to agree within 10 %.  The paper's 0.174 comes from a
+    Laplace experiment whose radii, radius definition and fit it does not
+    give."""
     _say("case Laplace test, G = 1.5")
-    gamma, c0, pts = _laplace_gamma(fm)
-    _say(f"  gamma = {gamma:.4f} (paper: 0.174), intercept {c0:.2e}")
-    assert gamma == pytest.approx(0.174, rel=0.15)
-    assert abs(c0) < 0.1 * max(p[1] for p in pts)
-    # bulk densities of the largest droplet against those printed in Sec. VI B
-    # (2.3 and 0.06, to the digits given there); the Laplace pressure of a
-    # finite droplet shifts them by a few percent (measured: 2.355 / 0.061
-    # inside, 0.066 / 2.320 outside)
+    pts = _laplace_points(fm)
+    inv_r = np.array([1.0 / p[0] for p in pts])
+    dps = np.array([p[1] for p in pts])
+    (gamma, c0), cov = np.polyfit(inv_r, dps, 1, cov=True)
+    sg, sc = float(np.sqrt(cov[0, 0])), float(np.sqrt(cov[1, 1]))
+    _say(f"  gamma = {gamma:.4f} +- {sg:.4f}, intercept {c0:.2e} +- {sc:.2e}")
+    assert abs(c0) <= 3 * sc
+    for R, dp, _, _ in pts:
+        assert abs(dp * R - gamma) <= 3 * sg + 3 * sc * R, R
+    g_mech, dense_mech = _mechanical_gamma()
+    dense = np.array([p[2][0] for p in pts])
+    _say(f"  mechanical gamma of the flat interface {g_mech:.4f} (dense phase {dense_mech:.4f}, droplets "
+         f"{dense.round(4)}); difference {(gamma - g_mech) / sg:.1f} fit errors")
+    assert gamma == pytest.approx(g_mech, rel=0.10)
+    # bulk densities against those printed in Sec. VI B (2.3 and 0.06, to the digits given there)
     rin, rout = pts[-1][2], pts[-1][3]
     assert rin[0] == pytest.approx(DENSE, rel=0.03) and rout[1] == pytest.approx(DENSE, rel=0.03)
     assert rin[1] == pytest.approx(LIGHT, rel=0.12) and rout[0] == pytest.approx(LIGHT, rel=0.12)
@@ -138,21 +168,29 @@ def test_capillary_spectrum(fm):
     """100 x 512 box, 50 x 512 stripe, k_BT = 1e-5, FP32: 1e5 steps of
     burn-in, then 2000 snapshots 1000 steps apart (2.1e6 steps in all, as in
     the paper).  For k = 2 pi n / 512, both interfaces' height spectra
-    against Eq. (91) with the paper's gamma = 0.174: band means of
-    k^2 <|h|^2> gamma / k_BT within 10 % of 1 for n in [5, 20) and [20, 80)
-    (k up to 0.98).  Snapshots 1000 steps apart are uncorrelated for n >= 5
-    (measured autocorrelation below 0.1), so the statistical error of a band
-    mean is about 0.5 %; measured: 0.94-0.96 and 0.98-0.99.  With the
-    Laplace gamma of this implementation (0.151) the ratios are 0.82 / 0.85:
-    the spectrum gives a gamma near the paper's value and the Laplace
-    reading is the one that differs.  n < 5 is left out: those modes lie
-    about 10 % below the law."""
-    _say("case capillary spectrum FP32, gamma 0.174")
+    against Eq. (91): band means of k^2 <|h|^2> gamma / k_BT for n in [5, 20)
+    and [20, 80) (k up to 0.98).  Snapshots 1000 steps apart are
+    uncorrelated for n >= 5 (measured autocorrelation below 0.1), so the
+    statistical error of a band mean is about 0.5 %.
+    With the paper's gamma = 0.174 the ratios are 0.94-0.96 and 0.98-0.99:
+    within 10 % of 1, the agreement the paper reports.  With the mechanical
+    surface tension of this very interface (the oracle's flat 100 / 50
+    stripe, pair-force virial: 0.161) the ratios are 0.88-0.89 and 0.91-0.92:
+    the interface fluctuates about 10 % less than Eq. (91) predicts from the
+    model's own gamma, the size of deviation the paper's conclusions (Sec.
+    VII) leave open for the diagonal noise approximation at interfaces;
+    asserted within 15 % of 1.  n < 5 is left out: those modes lie about
+    20 % below the law."""
+    _say("case capillary spectrum FP32")
     spec, k = _spectrum(fm, "f32", 7, 100000, 2000)
+    g_mech, _ = _mechanical_gamma(100, 50, 20000)
     for lo, hi in ((5, 20), (20, 80)):
         ratio = _band(spec, k, lo, hi, GAMMA_PAPER)
-        _say(f"  n in [{lo},{hi}): k^2 <|h|^2> gamma / k_BT = {ratio:.3f}")
+        ratio_m = _band(spec, k, lo, hi, g_mech)
+        _say(f"  n in [{lo},{hi}): k^2 <|h|^2> gamma / k_BT = {ratio:.3f} (gamma 0.174), {ratio_m:.3f} "
+             f"(mechanical gamma {g_mech:.4f})")
         assert ratio == pytest.approx(1.0, rel=0.10), (lo, hi)
+        assert ratio_m == pytest.approx(1.0, rel=0.15), (lo, hi)
 
 
 def test_capillary_spectrum_fp32_matches_fp64(fm):

@@ -47,8 +47,10 @@ def test_c0_equipartition_and_ideal_structure_factors(fm):
     """64x64 FP64, G = 0, tau = 1, k_BT = 1e-4, uniform start, seed 1: steps
     200..1000 sampled.  Modes a = 1..8 of both species within 1 % of
     equipartition; S(k) averaged over |k| > 1 (modes that have relaxed many
-    times over the run) within 2 % of the ideal values, S_rho_rho' within
-    2 % of S_rho_rho."""
+    times over the run) within 1 % of the ideal values (the target), S_rho_rho'
+    within 1 % of S_rho_rho.  Statistical error of these means: about 3000
+    wavevectors x 800 snapshots that decorrelate within a few steps at tau = 1,
+    well below 0.1 % (measured deviations: at most 0.1 %)."""
     kT = 1e-4
     p = fm.Params(lattice="d2q9", storage="f64", nx=64, ny=64, tau=(1.0, 1.0), tau_d=1.0, G=0.0, kT=kT, seed=1)
     lat = fm.Lattice(p)
@@ -69,12 +71,12 @@ def test_c0_equipartition_and_ideal_structure_factors(fm):
     S = {name: lat.sk(name)[0] for name in ("rho1rho1", "rho2rho2", "rho1rho2", "j1j1", "j2j2", "vbvb")}
     m = {k: float(v[sel].mean()) for k, v in S.items()}
     _say("c0 S(k) means over |k| > 1", m)
-    assert m["rho1rho1"] == pytest.approx(3 * kT, rel=0.02)
-    assert m["rho2rho2"] == pytest.approx(3 * kT, rel=0.02)
-    assert abs(m["rho1rho2"]) < 0.02 * 3 * kT
-    assert m["j1j1"] == pytest.approx(kT, rel=0.02)
-    assert m["j2j2"] == pytest.approx(kT, rel=0.02)
-    assert m["vbvb"] == pytest.approx(kT / 2.0, rel=0.02)
+    assert m["rho1rho1"] == pytest.approx(3 * kT, rel=0.01)
+    assert m["rho2rho2"] == pytest.approx(3 * kT, rel=0.01)
+    assert abs(m["rho1rho2"]) < 0.01 * 3 * kT
+    assert m["j1j1"] == pytest.approx(kT, rel=0.01)
+    assert m["j2j2"] == pytest.approx(kT, rel=0.01)
+    assert m["vbvb"] == pytest.approx(kT / 2.0, rel=0.01)
     lat.close()
 
 
@@ -82,10 +84,14 @@ def test_c1_structure_factors_vs_lattice_theory(fm):
     """1024^2 FP32, G = 0.5, tau = 0.8 / 1.2, k_BT = 1e-5, densities
     1 + U(-0.01, 0.01), seed 1: 1e4 steps, S(k) every 100 steps after 2000
     steps of burn-in (80 snapshots).  Bins of |k| in [0.3, 4.5) against the
-    discrete linear theory evaluated on 40 random wavevectors per bin: 3 %
-    (80 correlated snapshots of ~1e5 wavevectors per bin; the start's
-    perturbation has relaxed for |k| > 0.3).  Transport and ghost modes
-    within 1 % of equipartition."""
+    discrete linear theory averaged over 200 random wavevectors per bin
+    (the start's perturbation has relaxed for |k| > 0.3).  Bound per bin:
+    5 standard errors, with a floor of 0.5 %: the measured bin mean has
+    relative variance (1 + q) / (1 - q) / (snapshots x wavevectors), q =
+    r(k)^200 from the spectral radius r of the linear step (snapshots 100
+    steps apart are correlated through the slowest mode), and the theory's
+    bin mean carries the sampling error of its 200 wavevectors.  Transport
+    and ghost modes within 1 % of equipartition."""
     import workloads
     from lyapunov import LinearFLBE
     kT, G, tau = 1e-5, 0.5, (0.8, 1.2)
@@ -111,20 +117,33 @@ def test_c1_structure_factors_vs_lattice_theory(fm):
     kmag = np.sqrt(KX ** 2 + KY ** 2)
     L = LinearFLBE("d2q9", G=G, kT=kT, tau=tau, tau_d=1.0)
     rng = np.random.default_rng(7)
+    nsnap, every, npick = 80, 100, 200
     for lo, hi in ((0.3, 0.6), (0.6, 1.2), (1.2, 2.4), (2.4, 4.5)):
         sel = (kmag >= lo) & (kmag < hi)
         idx = np.argwhere(sel)
-        pick = idx[rng.choice(len(idx), size=40, replace=False)]
-        th = {k: 0.0 for k in S}
+        pick = idx[rng.choice(len(idx), size=npick, replace=False)]
+        samples = {k: [] for k in S}
+        corr = []
         for iy, ix in pick:
-            t = L.structure_factors([KX[iy, ix], KY[iy, ix]])
-            for k in th:
-                th[k] += t[k] / len(pick)
+            kv = [KX[iy, ix], KY[iy, ix]]
+            t = L.structure_factors(kv)
+            for k in samples:
+                samples[k].append(t[k])
+            q = L.spectral_radius(kv) ** (2 * every)
+            corr.append((1 + q) / (1 - q))
+        th = {k: float(np.mean(v)) for k, v in samples.items()}
+        # a real field's k and -k carry the same information: half the bin's wavevectors are independent
+        var_meas = float(np.mean(corr)) / (nsnap * (sel.sum() / 2))
         meas = {k: float(v[sel].mean()) for k, v in S.items()}
         _say(f"c1 bin [{lo},{hi}) measured", meas, "theory", th)
         for k in ("rho1rho1", "rho2rho2", "vbvb"):
-            assert meas[k] == pytest.approx(th[k], rel=0.03), (k, lo)
-        assert abs(meas["rho1rho2"] - th["rho1rho2"]) < 0.03 * th["rho1rho1"], lo
+            var_th = float(np.var(samples[k]) / npick) / th[k] ** 2
+            tol = max(5 * np.sqrt(var_meas + var_th), 0.005)
+            _say(f"   {k}: ratio {meas[k] / th[k]:.4f}, bound {tol:.4f}")
+            assert meas[k] == pytest.approx(th[k], rel=tol), (k, lo)
+        var_th = float(np.var(samples["rho1rho2"]) / npick) / th["rho1rho1"] ** 2
+        tol = max(5 * np.sqrt(var_meas + var_th), 0.005)
+        assert abs(meas["rho1rho2"] - th["rho1rho2"]) < tol * th["rho1rho1"], lo
 
 
 def _twin(fm, storage, phys, shape=(64, 64, 64), seed_init=1):

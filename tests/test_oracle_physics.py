@@ -373,3 +373,67 @@ def test_flat_interface_g15(orc):
     inside = np.where((frac > 0.01) & (frac < 0.99))[0]
     width = inside.max() - inside.min() + 1
     assert abs(width - gold["width"]) <= 2
+
+
+def _flat_interface(orc, lattice_id, n, width, ny=1, nz=1, steps=20000):
+    import workloads
+    gold = _golden("interface_g15.txt")
+    r1, r2 = workloads.stripe_density(n, ny * nz, width, gold["rho_dense"], gold["rho_light"])
+    shape = (nz, ny, n)
+    s = _sim(orc, lattice=lattice_id, nx=n, ny=ny, nz=nz, G=gold["G"], kT=0.0)
+    s.init_density(r1.reshape(shape), r2.reshape(shape))
+    s.step(steps)
+    return s, gold["G"]
+
+
+def _pair_virial(s, G):
+    """Volume-summed pair-force virial sum_pairs r_ij (x) f_ij of the lattice
+    force of Eq. (87): species 1 at r and species 2 at r + c_i interact with
+    the force -G w_i c_i rho_1(r) rho_2(r + c_i) on the first and its
+    opposite on the second, so the virial is G sum_r sum_i w_i c_i c_i
+    rho_1(r) rho_2(r + c_i) (a D x D tensor)."""
+    rho = s.moments()[0]
+    V = np.zeros((3, 3))
+    for i in range(s.Q):
+        shifted = np.roll(rho[1], shift=(-s.c[i, 2], -s.c[i, 1], -s.c[i, 0]), axis=(0, 1, 2))
+        V += G * s.w[i] * np.outer(s.c[i], s.c[i]) * np.sum(rho[0] * shifted)
+    return V, rho
+
+
+def test_flat_interface_mechanical_surface_tension(orc):
+    """Mechanical surface tension of the flat G = 1.5 interface of Sec. VI B
+    (the 100-site box with a 50-site stripe, the capillary run's geometry):
+    gamma = sum_x (P_N - P_T) / 2 over the box's two interfaces, with the
+    pressure tensor of the pair force of Eq. (87) (its virial) plus the
+    kinetic stress sum_i f_i c_i c_i.  Pins: (1) in a uniform phase the
+    virial is c_s^2 G rho_1 rho_2 per site, so with the isotropic kinetic
+    stress the bulk pressure is c_s^2 (rho_1 + rho_2 + G rho_1 rho_2); the
+    two coexisting phases have the same pressure (mechanical equilibrium);
+    (2) the kinetic stress of the steady interface is isotropic, so gamma is
+    the virial's anisotropy alone; (3) D3Q19 gives the same interface and the
+    same gamma (the force's projection on the normal, sum over c_x = +-1 of
+    w_i, is 1/6 on both lattices).  Measured: gamma = 0.1614 at bulk densities
+    2.350 / 0.0620; the paper quotes 0.174 from a Laplace experiment whose
+    radii and fit it does not give."""
+    cs2 = 1.0 / 3.0
+    gam = {}
+    for lattice_id, ny, nz in ((0, 1, 1), (1, 2, 2)):
+        s, G = _flat_interface(orc, lattice_id, 100, 50, ny=ny, nz=nz)
+        V, rho = _pair_virial(s, G)
+        n_sites = s.nsites
+        # (2) kinetic stress: isotropic in the plane of the interface and normal to it
+        f = s.populations().reshape(2, s.Q, -1)
+        K = np.einsum("ia,ib,sin->ab", s.c.astype(float), s.c.astype(float), f)
+        assert abs(K[0, 0] - K[1, 1]) <= 1e-8 * K[0, 0]
+        gam[lattice_id] = (V[0, 0] - V[1, 1]) / 2 / (n_sites / 100)  # per unit interface length
+        # (1) bulk pressures from the closed form are equal on both sides; the
+        # virial per site in the middle of a phase matches c_s^2 G rho_1 rho_2
+        r1, r2 = rho[0].reshape(-1, 100)[0], rho[1].reshape(-1, 100)[0]
+        p = cs2 * (r1 + r2 + G * r1 * r2)
+        assert p[50] == pytest.approx(p[0], rel=1e-9)
+        local = sum(G * s.w[i] * s.c[i, 1] ** 2 * r1[50] * np.roll(r2, -s.c[i, 0])[50] for i in range(s.Q))
+        assert local == pytest.approx(cs2 * G * r1[50] * r2[50], rel=1e-9)
+    assert gam[0] == pytest.approx(gam[1], rel=1e-6)
+    assert gam[0] == pytest.approx(0.1614, abs=5e-4)
+    # against the paper's Laplace value: within 10 % (7.3 % below it)
+    assert gam[0] == pytest.approx(0.174, rel=0.10)
