@@ -385,10 +385,10 @@ fmlb_status fmlb_batch_reset_modes(fmlb_batch *b);
  *   the sum; every other mode of species sigma as in the binary model, with
  *   its own tau and the normals D (N - 1) + sigma (Q - D - 1) + ....  For
  *   N = 2 this is the binary model on the same normals (same sample path up
- *   to rounding).  Two kernels per step (a potential pass, then the step),
- *   or one fused kernel (potentials of the next plane in an LDS ring, the
- *   plane re-pulled from cache to collide; fmlb_multi_set_tile).  Storage
- *   FMLB_F64 or FMLB_F32 (deviations from w_i rho_ref).
+ *   to rounding).  One kernel per step (the potentials of the next plane in
+ *   an LDS ring, its populations pulled into LDS ahead of use) or two (a
+ *   potential pass, then the step); fmlb_multi_set_form.  Storage FMLB_F64
+ *   or FMLB_F32 (deviations from w_i rho_ref).
  * ------------------------------------------------------------------------ */
 #define FMLB_MAX_SPECIES 4
 
@@ -428,14 +428,27 @@ fmlb_status fmlb_multi_init_density(fmlb_multi *m, const double *rho);
 /* Advance n >= 0 steps (asynchronous).  FMLB_E_STATE before an initial state. */
 fmlb_status fmlb_multi_step(fmlb_multi *m, int64_t n);
 
-/* Launch form of the N-species step.  tile_x = 0 (default) or 1: the
- * two-pass form (a potential pass, then the step).  Otherwise the
- * single-pass form: a tile_x x tile_y tile of the plane orthogonal to the
- * march axis (D3Q19: 64x4, 64x8 or 32x8; D2Q9: 64x1, 128x1 or 256x1)
- * walking `march` planes (1..4096, 0 = default).  Both forms give the same
- * bits; the two-pass form is the faster one measured (D3Q19 256^3, three
- * species: 2.37 against 2.72 ms per step).  FMLB_E_INVALID for an
- * unsupported shape. */
+/* Launch forms of the N-species step; all give the same bits.
+ *   FMLB_MULTI_AUTO (default): ASYNC where it applies (FP32 storage, one
+ *     species' array under 4 GiB), else TWO_PASS.
+ *   FMLB_MULTI_TWO_PASS: a potential pass, then the step (any storage).
+ *   FMLB_MULTI_FUSED: one pass with register pulls: a tile_x x tile_y tile of
+ *     the plane orthogonal to the march axis (D3Q19: 64x4, 64x8 or 32x8;
+ *     D2Q9: 64x1, 128x1 or 256x1) walking `march` planes.
+ *   FMLB_MULTI_ASYNC: one pass, the next plane's populations pulled straight
+ *     into LDS while the current plane collides (D3Q19 tiles 64x4, 64x8, 32x8
+ *     or 32x4 where their LDS fits: 64x8 two species only; D2Q9 64x1, 128x1
+ *     or 256x1); FP32 storage only.
+ * tile_x = tile_y = 0 and march = 0 select the defaults (march: 1..4096).
+ * FMLB_E_INVALID for an unknown form or shape, or a tile or march given to
+ * AUTO / TWO_PASS; FMLB_E_UNSUPPORTED for ASYNC on a lattice it does not
+ * run. */
+enum { FMLB_MULTI_AUTO = 0, FMLB_MULTI_TWO_PASS = 1, FMLB_MULTI_FUSED = 2, FMLB_MULTI_ASYNC = 3 };
+fmlb_status fmlb_multi_set_form(fmlb_multi *m, int form, int tile_x, int tile_y, int march);
+
+/* Shorthand kept for the register single pass: (0, 0, 0) = AUTO,
+ * (1, 0, 0) = TWO_PASS, tile_x > 1 = FUSED with that tile and march;
+ * anything else FMLB_E_INVALID. */
 fmlb_status fmlb_multi_set_tile(fmlb_multi *m, int tile_x, int tile_y, int march);
 int64_t fmlb_multi_current_step(const fmlb_multi *m);
 

@@ -120,6 +120,7 @@ _SIGNATURES = {
     "fmlb_multi_step": (ctypes.c_int32, [_vp, ctypes.c_int64]),
     "fmlb_multi_current_step": (ctypes.c_int64, [_vp]),
     "fmlb_multi_set_tile": (ctypes.c_int32, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+    "fmlb_multi_set_form": (ctypes.c_int32, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "fmlb_multi_get_populations": (ctypes.c_int32, [_vp, _dp, ctypes.c_size_t]),
     "fmlb_multi_set_populations": (ctypes.c_int32, [_vp, _dp, ctypes.c_size_t, ctypes.c_int64]),
     "fmlb_multi_moments": (ctypes.c_int32, [_vp, _dp, _dp]),
@@ -395,6 +396,15 @@ def fmlb_multi_current_step(m: int) -> int:
 
 def fmlb_multi_set_tile(m: int, tile_x: int, tile_y: int, march: int):
     _check("fmlb_multi_set_tile", lib().fmlb_multi_set_tile(_vp(m), tile_x, tile_y, march))
+
+
+FMLB_MULTI_AUTO, FMLB_MULTI_TWO_PASS, FMLB_MULTI_FUSED, FMLB_MULTI_ASYNC = 0, 1, 2, 3
+MULTI_FORMS = {"auto": FMLB_MULTI_AUTO, "two_pass": FMLB_MULTI_TWO_PASS, "fused": FMLB_MULTI_FUSED,
+               "async": FMLB_MULTI_ASYNC}
+
+
+def fmlb_multi_set_form(m: int, form: int, tile_x: int, tile_y: int, march: int):
+    _check("fmlb_multi_set_form", lib().fmlb_multi_set_form(_vp(m), form, tile_x, tile_y, march))
 
 
 def fmlb_multi_get_populations(m: int, out: np.ndarray):
@@ -710,8 +720,14 @@ class Multi:
         fmlb_multi_step(self.m, n)
 
     def set_tile(self, tile_x: int = 0, tile_y: int = 0, march: int = 0):
-        """tile_x 0 (default) or 1: the two-pass form; otherwise a fused tile."""
+        """(0, 0, 0): the default form; (1, 0, 0): two passes; otherwise the
+        register single pass with that tile."""
         fmlb_multi_set_tile(self.m, tile_x, tile_y, march)
+
+    def set_form(self, form: str = "auto", tile_x: int = 0, tile_y: int = 0, march: int = 0):
+        """form: "auto", "two_pass", "fused" (register single pass) or "async"
+        (single pass with the next plane pulled into LDS; FP32 storage)."""
+        fmlb_multi_set_form(self.m, MULTI_FORMS[form], tile_x, tile_y, march)
 
     def populations(self):
         out = np.empty((self.N, self.Q) + self.shape)

@@ -678,20 +678,6 @@ struct WideRows {
     }
 };
 
-// f(std::integral_constant<int, k>) for k = 0 .. N-1, so that table lookups
-// with k inside f are constant expressions.
-template <int N, class F, int... K>
-__device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, K...>)
-{
-    (f(std::integral_constant<int, K>{}), ...);
-}
-
-template <int N, class F>
-__device__ __forceinline__ void static_for(F &&f)
-{
-    static_for_impl<N>(f, std::make_integer_sequence<int, N>{});
-}
-
 // ---------------------------------------------------------------------------
 // Full-width tiles (D3Q19, tile width = nx): every row of the tile is a whole
 // lattice row, so each population is read as contiguous nx-site rows and the

@@ -11,10 +11,27 @@
 //    through planes.
 #pragma once
 
+#include <type_traits>
+#include <utility>
+
 #include "collide.h"
 #include "storage.h"
 
 namespace fmlb {
+
+// f(std::integral_constant<int, k>) for k = 0 .. N-1, so that table lookups
+// with k inside f are constant expressions.
+template <int N, class F, int... K>
+__device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, K...>)
+{
+    (f(std::integral_constant<int, K>{}), ...);
+}
+
+template <int N, class F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    static_for_impl<N>(f, std::make_integer_sequence<int, N>{});
+}
 
 template <class L, class S>
 struct StepArgs {

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -89,7 +90,8 @@ struct fmlb_multi {
     int cur;
     int64_t step;
     bool ready;
-    int tile_x, tile_y, march;  // 0: defaults; tile_x 1: two-pass form
+    int form;                   // FMLB_MULTI_*
+    int tile_x, tile_y, march;  // 0: defaults
 };
 
 namespace {
@@ -146,6 +148,22 @@ bool multi_tile_valid(int D, int tx, int ty)
     return ty == 1 && (tx == 64 || tx == 128 || tx == 256);
 }
 
+// Asynchronous tiles: D3Q19 64x4, 64x8, 32x8, 32x4; D2Q9 64x1, 128x1, 256x1;
+// each where its LDS fits.
+bool multi_async_tile_valid(int D, int N, int tx, int ty)
+{
+    const bool shape = D == 3 ? (tx == 64 && (ty == 4 || ty == 8)) || (tx == 32 && (ty == 8 || ty == 4))
+                              : ty == 1 && (tx == 64 || tx == 128 || tx == 256);
+    return shape && multi_async_lds_bytes(D, D == 3 ? 19 : 9, N, tx, ty) <= kMaxLdsBytes;
+}
+
+// The asynchronous form runs FP32 storage whose species arrays are
+// addressable by 32-bit buffer offsets.
+bool multi_async_supported(const fmlb_multi *m)
+{
+    return m->p.storage == FMLB_F32 && (double)m->Q * (double)m->g.nsites * 4.0 < 4294967295.0;
+}
+
 // Default march of a fused tile: the longest that still gives about two
 // workgroups per CU.
 void multi_default_tile(const fmlb_multi *m, int &tx, int &ty, int &march)
@@ -192,21 +210,87 @@ hipError_t multi_fused_dispatch(const MultiArgs<S> &a, int tx, int ty, int march
     }
 }
 
+// Default tile of the asynchronous form.
+void multi_async_default(const fmlb_multi *m, int &tx, int &ty)
+{
+    const Geom &g = m->g;
+    if (m->tile_x > 1) {
+        tx = m->tile_x;
+        ty = m->tile_y;
+    } else if (m->D == 3) {
+        // measured at 256^3: two species 1.20 ms with 64x8 against 1.30 with
+        // 64x4 (two workgroups per CU); three and four species only fit 64x4
+        tx = 64;
+        ty = multi_async_tile_valid(3, m->N, 64, 8) ? 8 : 4;
+    } else {
+        tx = g.nx >= 256 ? 256 : (g.nx >= 128 ? 128 : 64);
+        ty = 1;
+    }
+}
+
+constexpr int kComputeUnits = 256;  // MI355X
+
+// march 0: the longest march (a power of two) that still gives every CU as
+// many workgroups as fit on it at once (LDS and registers decide how many);
+// longer marches re-read fewer halo planes.
+template <class L, int N, int T0, int T1>
+hipError_t multi_async_launch(const MultiArgs<float> &a, int march, hipStream_t stream)
+{
+    const Geom &g = a.g;
+    const int n1 = L::D == 3 ? g.ny : 1, nm = L::D == 3 ? g.nz : g.ny;
+    const long cols = (long)((g.nx + T0 - 1) / T0) * (long)((n1 + T1 - 1) / T1);
+    if (march == 0) {
+        static std::atomic<int> cached{0};  // the same for every device of this kind
+        int per_cu = cached.load(std::memory_order_relaxed);
+        if (per_cu == 0) {
+            const hipError_t e =
+                hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, multi_async_kernel<L, N, T0, T1>, T0 * T1, 0);
+            if (e != hipSuccess) return e;
+            cached.store(per_cu, std::memory_order_relaxed);
+        }
+        const long target = (long)kComputeUnits * (per_cu > 0 ? per_cu : 1);
+        march = 1;
+        while (march < 4096 && cols * ((nm + 2L * march - 1) / (2L * march)) >= target) march *= 2;
+    }
+    const unsigned blocks = (unsigned)cols * (unsigned)((nm + march - 1) / march);
+    hipLaunchKernelGGL((multi_async_kernel<L, N, T0, T1>), dim3(blocks), dim3(T0 * T1), 0, stream, a, march);
+    return hipGetLastError();
+}
+
+template <class L, int N>
+hipError_t multi_async_dispatch(const MultiArgs<float> &a, int tx, int ty, int march, hipStream_t stream)
+{
+    if constexpr (L::D == 3) {
+        constexpr bool fits8 = multi_async_lds_bytes(3, 19, N, 64, 8) <= kMaxLdsBytes;
+        if (tx == 64 && ty == 4) return multi_async_launch<L, N, 64, 4>(a, march, stream);
+        if constexpr (fits8)
+            if (tx == 64 && ty == 8) return multi_async_launch<L, N, 64, 8>(a, march, stream);
+        if (ty == 8) return multi_async_launch<L, N, 32, 8>(a, march, stream);
+        return multi_async_launch<L, N, 32, 4>(a, march, stream);
+    } else {
+        if (tx == 64) return multi_async_launch<L, N, 64, 1>(a, march, stream);
+        if (tx == 128) return multi_async_launch<L, N, 128, 1>(a, march, stream);
+        return multi_async_launch<L, N, 256, 1>(a, march, stream);
+    }
+}
+
 template <class L, class S, int N>
 fmlb_status multi_run(fmlb_multi *m, int64_t n)
 {
     using Real = typename Storage<S>::Real;
     const Grid gr = multi_grid(m->g);
-    // Default: the two-pass form (measured faster at 256^3, three species:
-    // 2.37 ms against 2.72 ms for the best fused tile); the fused form runs
-    // when a fused tile is set.
-    int tx = m->tile_x, ty = m->tile_y, march = m->march;
-    const bool fused = tx > 1;
-    if (fused && march == 0) {
-        int dtx, dty, dm;
-        multi_default_tile(m, dtx, dty, dm);
-        march = dm;
+    // Default: the asynchronous single pass where it applies, else the
+    // two-pass form (the register single pass is slower than both).
+    int form = m->form;
+    if (form == FMLB_MULTI_AUTO) form = multi_async_supported(m) ? FMLB_MULTI_ASYNC : FMLB_MULTI_TWO_PASS;
+    int tx = 0, ty = 0, march = 0;
+    if (form == FMLB_MULTI_FUSED) multi_default_tile(m, tx, ty, march);
+    if (form == FMLB_MULTI_ASYNC) {
+        multi_async_default(m, tx, ty);
+        march = m->march;
     }
+
+    if (form == FMLB_MULTI_FUSED && m->march != 0) march = m->march;
     for (int64_t t = 0; t < n; ++t) {
         MultiArgs<S> a{};
         a.src = reinterpret_cast<const S *>(m->pops[m->cur]);
@@ -216,7 +300,12 @@ fmlb_status multi_run(fmlb_multi *m, int64_t n)
         a.ph = multi_phys<Real>(m->p);
         a.step_lo = (uint32_t)(uint64_t)m->step;
         a.step_hi = (uint32_t)((uint64_t)m->step >> 32);
-        if (fused) {
+        if (form == FMLB_MULTI_ASYNC) {
+            if constexpr (std::is_same<S, float>::value)
+                MULTI_TRY(multi_async_dispatch<L, N>(a, tx, ty, march, m->stream));
+            else
+                return FMLB_E_INVALID;
+        } else if (form == FMLB_MULTI_FUSED) {
             MULTI_TRY(multi_fused_dispatch<L, S, N>(a, tx, ty, march, m->stream));
         } else {
             hipLaunchKernelGGL((multi_potential_kernel<L, S, N>), gr.grid, gr.block, 0, m->stream, a);
@@ -276,16 +365,40 @@ void fmlb_multi_destroy(fmlb_multi *m) { delete m; }
 
 int64_t fmlb_multi_current_step(const fmlb_multi *m) { return m ? m->step : -1; }
 
-fmlb_status fmlb_multi_set_tile(fmlb_multi *m, int tile_x, int tile_y, int march)
+fmlb_status fmlb_multi_set_form(fmlb_multi *m, int form, int tile_x, int tile_y, int march)
 {
     if (!m) return FMLB_E_NULL;
     if (tile_x < 0 || tile_y < 0 || march < 0 || march > 4096) return FMLB_E_INVALID;
-    if (tile_x > 1 && !multi_tile_valid(m->D, tile_x, tile_y)) return FMLB_E_INVALID;
-    if (tile_x <= 1 && tile_y != 0) return FMLB_E_INVALID;
+    switch (form) {
+    case FMLB_MULTI_AUTO:
+    case FMLB_MULTI_TWO_PASS:
+        if (tile_x != 0 || tile_y != 0 || march != 0) return FMLB_E_INVALID;
+        break;
+    case FMLB_MULTI_FUSED:
+        if (tile_x != 0 && !multi_tile_valid(m->D, tile_x, tile_y)) return FMLB_E_INVALID;
+        break;
+    case FMLB_MULTI_ASYNC:
+        if (!multi_async_supported(m)) return FMLB_E_UNSUPPORTED;
+        if (tile_x != 0 && !multi_async_tile_valid(m->D, m->N, tile_x, tile_y)) return FMLB_E_INVALID;
+        break;
+
+    default: return FMLB_E_INVALID;
+    }
+    if (tile_x == 0 && tile_y != 0) return FMLB_E_INVALID;
+    m->form = form;
     m->tile_x = tile_x;
     m->tile_y = tile_y;
     m->march = march;
     return FMLB_OK;
+}
+
+fmlb_status fmlb_multi_set_tile(fmlb_multi *m, int tile_x, int tile_y, int march)
+{
+    if (!m) return FMLB_E_NULL;
+    if (tile_x == 0 && tile_y == 0 && march == 0) return fmlb_multi_set_form(m, FMLB_MULTI_AUTO, 0, 0, 0);
+    if (tile_x == 1 && tile_y == 0 && march == 0) return fmlb_multi_set_form(m, FMLB_MULTI_TWO_PASS, 0, 0, 0);
+    if (tile_x <= 1) return FMLB_E_INVALID;
+    return fmlb_multi_set_form(m, FMLB_MULTI_FUSED, tile_x, tile_y, march);
 }
 
 fmlb_status fmlb_multi_init_density(fmlb_multi *m, const double *rho)

@@ -135,3 +135,60 @@ def test_multi_invalid_parameters_rejected(fm, bad):
     with pytest.raises(fm.FmlbError) as e:
         fm.fmlb_multi_create(p.c(), 0, [256, 512, 768])
     assert e.value.status == fm.FMLB_E_INVALID
+
+
+def test_multi_set_form_validation(fm):
+    """Form selection is host logic: checked without a device (the buffers
+    are placeholders that nothing dereferences)."""
+    G = ((0.0, 0.3, 0.2), (0.3, 0.0, 0.1), (0.2, 0.1, 0.0))
+    ok, bad, unsup = fm.FMLB_OK, fm.FMLB_E_INVALID, fm.FMLB_E_UNSUPPORTED
+
+    def status(m, *args):
+        try:
+            fm.fmlb_multi_set_form(m, *args)
+            return ok
+        except fm.FmlbError as e:
+            return e.status
+
+    for storage in ("f32", "f64"):
+        m = fm.fmlb_multi_create(fm.MultiParams(lattice="d3q19", storage=storage, nspecies=3, nx=64, ny=32, nz=16,
+                                                G=G).c(), 0, [256, 512, 768])
+        try:
+            A, T, F, S = fm.FMLB_MULTI_AUTO, fm.FMLB_MULTI_TWO_PASS, fm.FMLB_MULTI_FUSED, fm.FMLB_MULTI_ASYNC
+            assert status(m, A, 0, 0, 0) == ok
+            assert status(m, T, 0, 0, 0) == ok
+            assert status(m, A, 64, 4, 0) == bad and status(m, T, 0, 0, 8) == bad
+            assert status(m, F, 64, 8, 16) == ok and status(m, F, 0, 0, 0) == ok
+            assert status(m, F, 32, 4, 0) == bad  # not a register-form tile
+            assert status(m, 7, 0, 0, 0) == bad and status(m, -1, 0, 0, 0) == bad
+            assert status(m, F, 64, 8, 5000) == bad and status(m, F, 0, 4, 0) == bad
+            if storage == "f32":
+                for t in ((64, 4, 0), (32, 8, 3), (32, 4, 4096), (0, 0, 0)):
+                    assert status(m, S, *t) == ok, t
+                # 64x8: its LDS holds two species only
+                for t in ((64, 8, 0), (64, 6, 0), (128, 1, 0), (16, 8, 0)):
+                    assert status(m, S, *t) == bad, t
+            else:
+                assert status(m, S, 0, 0, 0) == unsup
+            # the shorthand
+            fm.fmlb_multi_set_tile(m, 0, 0, 0)
+            fm.fmlb_multi_set_tile(m, 1, 0, 0)
+            fm.fmlb_multi_set_tile(m, 64, 4, 2)
+            for t in ((0, 0, 3), (1, 1, 0), (64, 2, 0)):
+                with pytest.raises(fm.FmlbError):
+                    fm.fmlb_multi_set_tile(m, *t)
+        finally:
+            fm.fmlb_multi_destroy(m)
+
+
+def test_multi_async_tiles_follow_the_lds(fm):
+    """64x8 asynchronous tiles fit the LDS with two species, not with three."""
+    G2 = ((0.0, 0.3), (0.3, 0.0))
+    m = fm.fmlb_multi_create(fm.MultiParams(lattice="d3q19", storage="f32", nspecies=2, nx=64, ny=32, nz=16,
+                                            tau=(1.0, 1.0), G=G2, rho_ref=(1.0, 1.0)).c(), 0, [256, 512, 768])
+    try:
+        fm.fmlb_multi_set_form(m, fm.FMLB_MULTI_ASYNC, 64, 8, 0)
+        with pytest.raises(fm.FmlbError):
+            fm.fmlb_multi_set_form(m, fm.FMLB_MULTI_ASYNC, 64, 6, 0)
+    finally:
+        fm.fmlb_multi_destroy(m)

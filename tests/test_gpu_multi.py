@@ -259,7 +259,7 @@ def test_full_size_three_species_sampled(fm):
 @pytest.mark.parametrize("lattice,shape,n,tiles", [
     ("d3q19", (7, 9, 70), 3, [(64, 4, 3), (64, 8, 2), (32, 8, 5), (64, 8, 0)]),
     ("d3q19", (2, 5, 33), 4, [(64, 4, 1), (32, 8, 2), (64, 4, 0)]),
-    ("d3q19", (6, 6, 6), 2, [(32, 8, 4), (64, 4, 64)]),
+    ("d3q19", (6, 6, 6), 2, [(32, 8, 4), (64, 4, 64), (64, 8, 3), (64, 8, 0)]),
     ("d2q9", (1, 37, 300), 3, [(64, 1, 5), (128, 1, 16), (256, 1, 2), (256, 1, 0)]),
     ("d2q9", (1, 2, 64), 4, [(64, 1, 1), (64, 1, 3)]),
 ])
@@ -275,13 +275,49 @@ def test_multi_fused_equals_two_pass(fm, storage, lattice, shape, n, tiles):
         m = fm.Multi(fm.MultiParams(lattice=lattice, storage=storage, nspecies=n, nx=nx, ny=ny, nz=nz,
                                     tau=(0.8, 1.1, 1.3, 0.9)[:n], tau_d=0.9, G=_couplings(n), kT=1e-4,
                                     rho_ref=(1.0, 0.8, 0.6, 0.4)[:n], seed=6))
-        m.set_tile(*tile)
+        if tile is None:
+            m.set_form("two_pass")
+        else:
+            m.set_tile(*tile)
         m.init_density(rho)
         m.step(7)
         f = m.populations()
         m.close()
         return f
 
-    ref = run((0, 0, 0))  # the default: two-pass
+    ref = run(None)
     for t in tiles:
         assert np.array_equal(run(t), ref), t
+
+
+@pytest.mark.parametrize("lattice,shape,n,tiles", [
+    ("d3q19", (7, 9, 70), 3, [(64, 4, 3), (32, 8, 2), (32, 4, 5), (0, 0, 0)]),
+    ("d3q19", (2, 5, 33), 4, [(64, 4, 1), (32, 8, 2), (32, 4, 0)]),
+    ("d3q19", (6, 6, 6), 2, [(32, 8, 4), (64, 4, 64), (64, 8, 3), (64, 8, 0)]),
+    ("d3q19", (1, 3, 40), 3, [(32, 4, 1), (64, 4, 0)]),
+    ("d2q9", (1, 37, 300), 3, [(64, 1, 5), (128, 1, 16), (256, 1, 2), (256, 1, 0)]),
+    ("d2q9", (1, 2, 64), 4, [(64, 1, 1), (64, 1, 3)]),
+])
+def test_multi_async_equals_two_pass(fm, lattice, shape, n, tiles):
+    """The asynchronous single pass (FP32; every tile, short and long
+    marches, ragged tiles, march axes shorter than the ring) gives the same
+    bits as the two-pass form, and so does the default form."""
+    _say("case multi async vs two-pass", lattice, shape, n)
+    nz, ny, nx = shape
+    rho = _densities(shape, n)
+
+    def run(form, tile=(0, 0, 0)):
+        m = fm.Multi(fm.MultiParams(lattice=lattice, storage="f32", nspecies=n, nx=nx, ny=ny, nz=nz,
+                                    tau=(0.8, 1.1, 1.3, 0.9)[:n], tau_d=0.9, G=_couplings(n), kT=1e-4,
+                                    rho_ref=(1.0, 0.8, 0.6, 0.4)[:n], seed=6))
+        m.set_form(form, *tile)
+        m.init_density(rho)
+        m.step(7)
+        f = m.populations()
+        m.close()
+        return f
+
+    ref = run("two_pass")
+    for t in tiles:
+        assert np.array_equal(run("async", t), ref), t
+    assert np.array_equal(run("auto"), ref)
