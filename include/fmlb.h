@@ -340,15 +340,23 @@ fmlb_status fmlb_batch_init_density(fmlb_batch *b, int r, const double *rho1, co
  * replica has been initialised. */
 fmlb_status fmlb_batch_step(fmlb_batch *b, int64_t n, int use_graph);
 
-/* Work-list shape: tile_x sites per workgroup row (64, 128 or 256) and
- * `march` rows walked per item (1..4096); 0 = default for each (the widest
- * tile at least half the replicas fill; one row per item for batches of
- * fewer than about 2000 tile rows, up to 16 above).  Results do
- * not depend on it.  Discards a captured graph. */
+/* Work-list shape (results do not depend on it; discards a captured graph):
+ *   tile_x = FMLB_BATCH_PACKED (T = 256) or FMLB_BATCH_PACKED_512 (T = 512):
+ *     packed sites.  A workgroup of T threads walks a contiguous run of a
+ *     replica's sites in row-major order, T sites per block and `march`
+ *     blocks per item, for replicas up to (T + 1) / 2 wide (128 or 256);
+ *     wider replicas get 256-site one-row tiles of `march` rows in a second
+ *     launch.
+ *   tile_x = 64, 128 or 256: one-row tiles of tile_x sites, `march` rows
+ *     per item, for every replica.
+ * march 1..4096.  0 = default for each: FMLB_BATCH_PACKED_512, with the
+ * longest march up to 16 that leaves about 2048 items. */
+#define FMLB_BATCH_PACKED 1
+#define FMLB_BATCH_PACKED_512 2
 fmlb_status fmlb_batch_set_tile(fmlb_batch *b, int tile_x, int march);
 
-/* Tile autotuner: times every supported work-list shape (tile_x 64, 128,
- * 256 x march 1, 2, 4, 8, 16, 32, 64) over `reps` recomputations of the next step
+/* Tile autotuner: times every supported work-list shape (tile_x packed 256
+ * and 512, 64, 128, 256 x march 1, 2, 4, 8, 16, 32, 64) over `reps` recomputations of the next step
  * (the state and the step counter are left unchanged: each trial re-reads
  * the current state and overwrites the other buffer), keeps the fastest and
  * reports it.  Synchronises.  FMLB_E_STATE until every replica is

@@ -398,6 +398,7 @@ def fmlb_multi_set_tile(m: int, tile_x: int, tile_y: int, march: int):
     _check("fmlb_multi_set_tile", lib().fmlb_multi_set_tile(_vp(m), tile_x, tile_y, march))
 
 
+FMLB_BATCH_PACKED, FMLB_BATCH_PACKED_512 = 1, 2
 FMLB_MULTI_AUTO, FMLB_MULTI_TWO_PASS, FMLB_MULTI_FUSED, FMLB_MULTI_ASYNC = 0, 1, 2, 3
 MULTI_FORMS = {"auto": FMLB_MULTI_AUTO, "two_pass": FMLB_MULTI_TWO_PASS, "fused": FMLB_MULTI_FUSED,
                "async": FMLB_MULTI_ASYNC}
@@ -611,6 +612,10 @@ class Batch:
         fmlb_batch_step(self.b, n, use_graph)
 
     def set_tile(self, tile_x: int = 0, march: int = 0):
+        """tile_x: FMLB_BATCH_PACKED / FMLB_BATCH_PACKED_512 (runs of 256 / 512
+        consecutive sites per block, replicas up to 128 / 256 wide), 64, 128
+        or 256 (one-row tiles); march: blocks or rows per item; 0 =
+        defaults."""
         fmlb_batch_set_tile(self.b, tile_x, march)
 
     def autotune(self, reps: int = 10):

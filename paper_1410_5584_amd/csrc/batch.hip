@@ -155,6 +155,212 @@ __global__ __launch_bounds__(T0) void batch_step_kernel(float *bufA, float *bufB
         fused_tile<D2Q9, float, T0, 1>(a, t0, 0, mbeg, mend);
 }
 
+// Packed sites: one workgroup of T threads walks a contiguous run of a
+// replica's sites in row-major order, T sites per block (thread t: logical
+// site l0 + k T + t of block k), so replicas of any width below T fill the
+// lanes that one-row tiles leave idle (a 256-wide tile on a width-40
+// replica runs 40 of its 256 lanes; here only a replica's last block is
+// partly idle).  Logical sites count on past the lattice's end: site l is
+// (l mod L, (l div L) mod ny), which is the periodic image in y, and a
+// neighbour's logical index is l + c_y L + c_x (+-L where x wraps), at most
+// 2L - 1 sites away (a row end's neighbour across the wrap in the next or
+// previous row).  The asynchronous tile walk of the single lattice
+// otherwise: block k+1's populations go straight from memory into LDS
+// while block k collides; the densities enter a ring of four blocks
+// indexed by (l - l0 + T) mod 4T, so with 2L - 1 <= T every neighbour of
+// block k is in blocks k-1, k or k+1.  A thread stores only sites of its
+// item.  Same
+// helpers as the single lattice (moments, lattice_acceleration,
+// collide_site): every replica evolves bit for bit as it would alone.
+template <int T>
+__device__ __forceinline__ void batch_pack_walk(const StepArgs<D2Q9, float> &a, long l0, long l1)
+{
+    using Lt = D2Q9;
+    using Real = float;
+    using Raw = uint32_t;
+    constexpr int Q = Lt::Q;
+    constexpr int RING = 4 * T;
+    __shared__ Real ring[2][RING];
+    __shared__ Raw own[2 * Q][T];
+
+    const int L = a.g.nx, ny = a.g.ny;
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const long nblk = (l1 - l0 + T - 1) / T;
+    const uint32_t pop_bytes = (uint32_t)a.g.nsites * 4u;
+    __amdgpu_buffer_rsrc_t rsrc[2], rdst[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        rsrc[s] = __builtin_amdgcn_make_buffer_rsrc((void *)(a.src + (size_t)s * Q * a.g.nsites), 0,
+                                                    (int)(Q * pop_bytes), kBufferWord3);
+        rdst[s] = __builtin_amdgcn_make_buffer_rsrc((void *)(a.dst + (size_t)s * Q * a.g.nsites), 0,
+                                                    (int)(Q * pop_bytes), kBufferWord3);
+    }
+    const Real ref[2] = {a.ref[0], a.ref[1]};
+    // (x, y) of logical site l, and the same T sites further on
+    const long span = (long)L * ny;
+    auto coords = [&](long l, int &x, int &y) {
+        const long m = ((l % span) + span) % span;
+        y = (int)(m / L);
+        x = (int)(m - (long)y * L);
+    };
+    const int dxb = T % L, dyb = T / L;
+    auto advance = [&](int x, int y, int &x2, int &y2) {
+        x2 = x + dxb;
+        y2 = y + dyb;
+        if (x2 >= L) {
+            x2 -= L;
+            y2 += 1;
+        }
+        y2 = (int)((unsigned)y2 % (unsigned)ny);
+    };
+    auto pull_off = [&](int x, int y, int i) __attribute__((always_inline)) -> uint32_t {
+        const int xs = wrap(x, -Lt::cx[i], L);
+        const int ys = wrap(y, -Lt::cy[i], ny);
+        return ((uint32_t)xs + (uint32_t)L * (uint32_t)ys) * 4u;
+    };
+    auto pull = [&](int x, int y, Real (&f)[2][Q]) __attribute__((always_inline)) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const uint32_t voff = pull_off(x, y, i);
+#pragma unroll
+            for (int s = 0; s < 2; ++s) f[s][i] = BufIO<float>::load(rsrc[s], voff, (uint32_t)i * pop_bytes);
+        }
+    };
+    auto dma = [&](int s, int x, int y) __attribute__((always_inline)) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            lds_void_t *dst = (lds_void_t *)(&own[s * Q + i][0] + wave * 64);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc[s], dst, 4, pull_off(x, y, i), (uint32_t)i * pop_bytes, 0, 0);
+        }
+    };
+    // ring position of block k's thread-t site
+    auto rpos = [&](long k) { return (int)(((k + 1) * T + tid) & (RING - 1)); };
+
+    Real cur[2][Q], rc[2], jc[2][3];
+    // Prologue: densities of blocks -1 and 0, populations and moments of
+    // block 0 (register pulls), then the asynchronous pull of block 1.
+#pragma unroll 1
+    for (int k = -1; k <= 0; ++k) {
+        int x, y;
+        coords(l0 + (long)k * T + tid, x, y);
+        Real f[2][Q];
+        pull(x, y, f);
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            Real r, j[3];
+            moments<Lt, Real>(f[s], r, j);
+            ring[s][rpos(k)] = r;
+            if (k == 0) {
+                rc[s] = r;
+#pragma unroll
+                for (int al = 0; al < 3; ++al) jc[s][al] = j[al];
+#pragma unroll
+                for (int i = 0; i < Q; ++i) cur[s][i] = f[s][i];
+            }
+        }
+    }
+    int xc, yc, xn, yn;  // this thread's site in block k and block k+1
+    coords(l0 + tid, xc, yc);
+    advance(xc, yc, xn, yn);
+    dma(0, xn, yn);
+    dma(1, xn, yn);
+
+#pragma unroll 1
+    for (long k = 0; k < nblk; ++k) {
+        // Rows of block k+1 have landed.
+        __builtin_amdgcn_s_waitcnt(kWaitVm0);
+        Real nxt[2][Q], rn[2], jn[2][3];
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int i = 0; i < Q; ++i) nxt[s][i] = __builtin_bit_cast(float, own[s * Q + i][tid]);
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            moments<Lt, Real>(nxt[s], rn[s], jn[s]);
+            ring[s][rpos(k + 1)] = rn[s];
+        }
+        // Workgroup barrier for the density ring only.
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
+        __builtin_amdgcn_s_barrier();
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+
+        // Ring positions of the neighbours: logical offset c_y L + c_x, with
+        // +-L where x wraps.
+        const int me = rpos(k);
+        auto nb = [&](int i, int s) -> Real {
+            const int cx = Lt::cx[i], cy = Lt::cy[i];
+            const int dx = cx == 0 ? 0 : (cx > 0 ? (xc == L - 1 ? 1 - L : 1) : (xc == 0 ? L - 1 : -1));
+            return ring[s][(me + cy * L + dx) & (RING - 1)];
+        };
+        Real acc[2][3];
+        lattice_acceleration<Lt, Real>(nb, a.ph.negG, acc);
+        // Every LDS read of this iteration is done: the row loads of block k+2.
+        const bool more = k + 1 < nblk;
+        int x2, y2;
+        advance(xn, yn, x2, y2);
+        __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
+        __builtin_amdgcn_sched_barrier(0);
+        if (more) dma(0, x2, y2);
+        __builtin_amdgcn_sched_barrier(0);
+        const bool store = l0 + k * T + tid < l1;
+        const uint32_t site = (uint32_t)xc + (uint32_t)L * (uint32_t)yc;
+        const uint32_t voff = site * 4u;
+        collide_site<Lt, Real>(cur, rc, jc, acc, a.ph, ref, Counter{site, a.step_lo, a.step_hi}, [&](int s, auto &fs) {
+            if (s == 0) {
+                __builtin_amdgcn_sched_barrier(0);
+                if (more) dma(1, x2, y2);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            if (store) {
+#pragma unroll
+                for (int i = 0; i < Q; ++i)
+                    store_stepped<float>(fs[i], rdst[s], voff, (uint32_t)i * pop_bytes, site, (uint32_t)(s * Q + i),
+                                         a.step_lo, a.ph.key0, a.ph.key1);
+            }
+        });
+        xc = xn;
+        yc = yn;
+        xn = x2;
+        yn = y2;
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            rc[s] = rn[s];
+#pragma unroll
+            for (int al = 0; al < 3; ++al) jc[s][al] = jn[s][al];
+#pragma unroll
+            for (int i = 0; i < Q; ++i) cur[s][i] = nxt[s][i];
+        }
+    }
+}
+
+// Packed-site items: tile_chunk holds the item's index among its replica's
+// items, each `chunk` blocks of T sites.
+template <int T>
+__global__ __launch_bounds__(T) void batch_pack_kernel(float *bufA, float *bufB, const BatchRep *reps,
+                                                       const BatchItem *items, unsigned nitems,
+                                                       const int64_t *step_dev, int offset, int chunk)
+{
+    const BatchItem it = items[xcd_contiguous(blockIdx.x, nitems)];
+    const BatchRep &R = reps[it.rep];
+    const int64_t step = *step_dev + offset;
+    const bool odd = (step & 1) != 0;
+    StepArgs<D2Q9, float> a{};
+    a.src = (odd ? bufB : bufA) + R.off;
+    a.dst = (odd ? bufA : bufB) + R.off;
+    a.rho = nullptr;
+    a.g = R.g;
+    a.ph = R.ph;
+    a.ref[0] = R.ref[0];
+    a.ref[1] = R.ref[1];
+    a.step_lo = (uint32_t)(uint64_t)step;
+    a.step_hi = (uint32_t)((uint64_t)step >> 32);
+    const long len = (long)T * chunk;
+    const long l0 = (long)it.tile_chunk * len;
+    batch_pack_walk<T>(a, l0, min(l0 + len, (long)R.g.nsites));
+}
+
 // Advances the device step counter (one lane, vector store).
 __global__ void batch_advance_kernel(int64_t *step_dev, int n)
 {
@@ -179,8 +385,9 @@ struct fmlb_batch {
     unsigned char *scratch;
     BatchLayout lay;
     int64_t step;
-    int tile_x, chunk;
+    int tile_x, chunk;  // tile_x FMLB_BATCH_PACKED(_512): packed sites, else one-row tiles
     unsigned nitems;
+    unsigned npack;     // packed-site items, at the front of the work list
     hipGraphExec_t gexec;
     hipStream_t cap_stream;
     int64_t mode_samples;
@@ -194,36 +401,68 @@ T *bscr(fmlb_batch *b, size_t off)
     return reinterpret_cast<T *>(b->scratch + off);
 }
 
-bool batch_tile_valid(int tx) { return tx == 64 || tx == 128 || tx == 256; }
+constexpr int kPackedTile = FMLB_BATCH_PACKED;         // packed sites, 256 threads
+constexpr int kPackedTile512 = FMLB_BATCH_PACKED_512;  // packed sites, 512 threads
 
-// Default tile: the widest one that at least half the replicas fill.
-// Default march: as for a single D2Q9 lattice, one row per item while the
-// whole batch has fewer than about 2000 tile rows (few small replicas are
-// bound by the latency of a row), then up to 16 (a single 100 x 512 replica:
-// 34 -> 7 us per step).
-void batch_default_shape(const fmlb_batch *b, int &tx, int &chunk)
+bool batch_tile_valid(int tx)
 {
-    std::vector<int> nx;
-    for (const auto &p : b->p) nx.push_back(p.nx);
-    std::sort(nx.begin(), nx.end());
-    const int med = nx[nx.size() / 2];
-    tx = med >= 256 ? 256 : (med >= 128 ? 128 : 64);
-    long rows = 0;
-    for (const auto &p : b->p) rows += (long)((p.nx + tx - 1) / tx) * (long)p.ny;
-    chunk = 1;
-    while (chunk < 16 && rows / (2L * chunk) >= 512) chunk *= 2;
-    if (chunk < 4) chunk = 1;
+    return tx == kPackedTile || tx == kPackedTile512 || tx == 64 || tx == 128 || tx == 256;
 }
 
+int pack_threads(int tx) { return tx == kPackedTile512 ? 512 : 256; }
+
+// Widest replica packed in blocks of T sites (a neighbour within one block).
+constexpr int pack_max_width(int T) { return (T + 1) / 2; }
+
+// Packed-site items of replica p for `chunk` blocks of T sites per item (0:
+// too wide to pack).
+long pack_items(const fmlb_params &p, int T, int chunk)
+{
+    if (p.nx > pack_max_width(T)) return 0;
+    const long len = (long)T * chunk;
+    return ((long)p.nx * p.ny + len - 1) / len;
+}
+
+// Default: packed sites in blocks of 512, with the longest march (blocks per
+// item, up to 16) that still leaves about 2048 items (eight per CU).
+void batch_default_shape(const fmlb_batch *b, int &tx, int &chunk)
+{
+    tx = kPackedTile512;
+    chunk = 1;
+    for (;;) {
+        long items = 0;
+        for (const auto &p : b->p)
+            items += p.nx > pack_max_width(512) ? (long)((p.nx + 255) / 256) * ((p.ny + 2L * chunk - 1) / (2L * chunk))
+                                                 : pack_items(p, 512, 2 * chunk);
+        if (chunk >= 16 || items < 2048) break;
+        chunk *= 2;
+    }
+}
+
+// The work list: packed tx puts the packed-site items of every replica up to
+// pack_max_width(T) wide first (the item's index among its replica's items),
+// then one-row 256-wide tiles of `chunk` rows for wider replicas; other tx:
+// one-row tiles of tx sites and `chunk` rows for every replica.
 fmlb_status build_items(fmlb_batch *b, int tx, int chunk)
 {
     std::vector<BatchItem> items;
+    unsigned npack = 0;
+    const bool packed = tx == kPackedTile || tx == kPackedTile512;
+    const int T = pack_threads(tx);
+    if (packed) {
+        for (int r = 0; r < b->n; ++r)
+            for (long i = 0; i < pack_items(b->p[r], T, chunk); ++i) items.push_back(BatchItem{(uint32_t)r, (uint32_t)i});
+        npack = (unsigned)items.size();
+    }
+    const int wt = packed ? 256 : tx;
     for (int r = 0; r < b->n; ++r) {
-        const int tiles = (b->p[r].nx + tx - 1) / tx, chunks = (b->p[r].ny + chunk - 1) / chunk;
+        if (packed && b->p[r].nx <= pack_max_width(T)) continue;
+        const int tiles = (b->p[r].nx + wt - 1) / wt, chunks = (b->p[r].ny + chunk - 1) / chunk;
         for (int ck = 0; ck < chunks; ++ck)
             for (int t = 0; t < tiles; ++t) items.push_back(BatchItem{(uint32_t)r, ((uint32_t)t << 16) | (uint32_t)ck});
     }
     if (items.size() > b->lay.max_items || items.empty()) return FMLB_E_INVALID;
+    b->npack = npack;
     BATCH_TRY(hipMemcpyAsync(bscr<BatchItem>(b, b->lay.items), items.data(), items.size() * sizeof(BatchItem),
                              hipMemcpyHostToDevice, b->stream));
     BATCH_TRY(hipStreamSynchronize(b->stream));
@@ -243,6 +482,18 @@ fmlb_status launch_batch_step(fmlb_batch *b, int offset, hipStream_t stream)
     const BatchRep *reps = bscr<BatchRep>(b, b->lay.reps);
     const BatchItem *items = bscr<BatchItem>(b, b->lay.items);
     switch (b->tile_x) {
+    case kPackedTile:
+    case kPackedTile512:
+        if (b->npack > 0 && b->tile_x == kPackedTile)
+            hipLaunchKernelGGL(batch_pack_kernel<256>, dim3(b->npack), dim3(256), 0, stream, b->buf[0], b->buf[1], reps,
+                               items, b->npack, sd, offset, b->chunk);
+        if (b->npack > 0 && b->tile_x == kPackedTile512)
+            hipLaunchKernelGGL(batch_pack_kernel<512>, dim3(b->npack), dim3(512), 0, stream, b->buf[0], b->buf[1], reps,
+                               items, b->npack, sd, offset, b->chunk);
+        if (b->nitems > b->npack)
+            hipLaunchKernelGGL(batch_step_kernel<256>, dim3(b->nitems - b->npack), dim3(256), 0, stream, b->buf[0],
+                               b->buf[1], reps, items + b->npack, b->nitems - b->npack, sd, offset, b->chunk);
+        break;
     case 64:
         hipLaunchKernelGGL(batch_step_kernel<64>, dim3(b->nitems), dim3(64), 0, stream, b->buf[0], b->buf[1],
                            reps, items, b->nitems, sd, offset, b->chunk);
@@ -446,7 +697,7 @@ fmlb_status fmlb_batch_autotune(fmlb_batch *b, int reps, int *tile_x, int *march
     if (reps < 1 || reps > 1000) return FMLB_E_INVALID;
     for (char rd : b->ready)
         if (!rd) return FMLB_E_STATE;
-    static const int kTiles[] = {64, 128, 256};
+    static const int kTiles[] = {kPackedTile, kPackedTile512, 64, 128, 256};
     static const int kMarch[] = {1, 2, 4, 8, 16, 32, 64};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     BATCH_TRY(hipEventCreate(&e0));

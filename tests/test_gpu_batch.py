@@ -127,7 +127,8 @@ def test_full_size_c4_sampled(fm, orc):
     b.close()
 
 
-@pytest.mark.parametrize("tile,march", [(64, 1), (128, 5), (256, 16), (64, 200)])
+@pytest.mark.parametrize("tile,march", [(64, 1), (128, 5), (256, 16), (64, 200), (1, 1), (1, 3), (1, 64), (2, 1),
+                                        (2, 5)])
 def test_batch_work_list_shape_invariance(fm, tile, march):
     _say("case batch tile", tile, march)
     b0, _ = _batch(fm)
@@ -139,6 +140,28 @@ def test_batch_work_list_shape_invariance(fm, tile, march):
         assert np.array_equal(b0.populations(r), b1.populations(r)), r
     b0.close()
     b1.close()
+
+
+@pytest.mark.parametrize("tile", [1, 2])
+def test_batch_packed_widths_at_the_limit(fm, tile):
+    """Packed sites reach a neighbour 2 nx - 1 sites away (a row end across
+    the x wrap, one row up or down): replicas at and beside the widest packed
+    width of each block size (128 for 256 threads, 256 for 512), and wider
+    ones on the one-row tiles of the same launch, evolve bit for bit as
+    alone."""
+    _say("case batch packed widths, tile", tile)
+    reps = [(w, 6, (0.9, 1.1), 1.0, 0.6, 1e-4, 40 + k) for k, w in enumerate((127, 128, 129, 200, 255, 256, 257))]
+    b, ps = _batch(fm, reps)
+    b.set_tile(tile, 3)
+    b.step(5)
+    for r, p in enumerate(ps):
+        lat = fm.Lattice(p)
+        lat.init_density(*_densities(p, r))
+        lat.step(5)
+        single = lat.populations()
+        lat.close()
+        assert np.array_equal(b.populations(r), single), (r, p.nx)
+    b.close()
 
 
 def test_batch_graph_replays_equal_direct_launches(fm):
