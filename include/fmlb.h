@@ -314,7 +314,9 @@ typedef struct fmlb_batch fmlb_batch;
 
 /* Bytes of buffer `which` (FMLB_BUF_*) for n replicas p[0..n-1]; 0 if any
  * p[r] is not a valid D2Q9 / FMLB_F32 lattice (flags: FMLB_NOISE_* bits only)
- * or n is outside [1, 65535]. */
+ * or n is outside [1, 65535].  POPS_A / POPS_B: per replica 2 x 9 population
+ * arrays of nx ny floats each padded to a multiple of 64 (so that every array
+ * starts on a 256-byte boundary). */
 size_t fmlb_batch_required_bytes(const fmlb_params *p, int n, int which);
 
 /* Borrow three 256-byte-aligned device buffers of at least the required

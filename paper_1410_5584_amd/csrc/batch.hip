@@ -60,13 +60,20 @@ struct BatchItem {
     uint32_t tile_chunk;  // tile index << 16 | chunk index
 };
 
+// Elements per population array of a replica: the site count rounded up to
+// 64 (256 bytes), so that every array starts on a cache-line boundary (an
+// odd site count otherwise shifts every array but the first: 231 replicas
+// of 181^2 ran at 0.281 ms per step against 0.214-0.224 for power-of-two
+// widths of the same total size).
+size_t replica_pitch(const fmlb_params &p) { return ((size_t)p.nx * p.ny + 63) & ~(size_t)63; }
+
 bool valid_replica(const fmlb_params &p)
 {
     if (p.lattice != FMLB_D2Q9 || p.storage != FMLB_F32) return false;
     if (p.flags & ~(uint32_t)(FMLB_NOISE_OFF | FMLB_NOISE_NO_SDF)) return false;
     if (p.nx < 1 || p.ny < 1 || p.nz != 1) return false;
     if (p.nx > 65535 * kMinTile || p.ny > 65535) return false;
-    if ((double)p.nx * p.ny * kQ * 2 * 4 >= 4294967295.0) return false;
+    if ((double)replica_pitch(p) * kQ * 2 * 4 >= 4294967295.0) return false;
     if (!(p.tau[0] > 0.5) || !(p.tau[1] > 0.5) || !(p.tau_d > 0.5)) return false;
     if (!std::isfinite(p.tau[0]) || !std::isfinite(p.tau[1]) || !std::isfinite(p.tau_d)) return false;
     if (!(p.kT >= 0.0) || !std::isfinite(p.kT) || !std::isfinite(p.G)) return false;
@@ -187,13 +194,13 @@ __device__ __forceinline__ void batch_pack_walk(const StepArgs<D2Q9, float> &a, 
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const long nblk = (l1 - l0 + T - 1) / T;
-    const uint32_t pop_bytes = (uint32_t)a.g.nsites * 4u;
+    const uint32_t pop_bytes = (uint32_t)a.g.pitch * 4u;
     __amdgpu_buffer_rsrc_t rsrc[2], rdst[2];
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-        rsrc[s] = __builtin_amdgcn_make_buffer_rsrc((void *)(a.src + (size_t)s * Q * a.g.nsites), 0,
+        rsrc[s] = __builtin_amdgcn_make_buffer_rsrc((void *)(a.src + (size_t)s * Q * a.g.pitch), 0,
                                                     (int)(Q * pop_bytes), kBufferWord3);
-        rdst[s] = __builtin_amdgcn_make_buffer_rsrc((void *)(a.dst + (size_t)s * Q * a.g.nsites), 0,
+        rdst[s] = __builtin_amdgcn_make_buffer_rsrc((void *)(a.dst + (size_t)s * Q * a.g.pitch), 0,
                                                     (int)(Q * pop_bytes), kBufferWord3);
     }
     const Real ref[2] = {a.ref[0], a.ref[1]};
@@ -558,7 +565,7 @@ size_t fmlb_batch_required_bytes(const fmlb_params *p, int n, int which)
     size_t pops = 0;
     for (int r = 0; r < n; ++r) {
         if (!valid_replica(p[r])) return 0;
-        pops += align256(2 * (size_t)kQ * p[r].nx * p[r].ny * sizeof(float));
+        pops += align256(2 * (size_t)kQ * replica_pitch(p[r]) * sizeof(float));
     }
     switch (which) {
     case FMLB_BUF_POPS_A:
@@ -597,12 +604,12 @@ fmlb_status fmlb_batch_create(const fmlb_params *p, int n, void *hip_stream, voi
     for (int r = 0; r < n; ++r) {
         BatchRep R{};
         R.off = off;
-        R.g = Geom{p[r].nx, p[r].ny, 1, (size_t)p[r].nx * p[r].ny};
+        R.g = Geom{p[r].nx, p[r].ny, 1, (size_t)p[r].nx * p[r].ny, replica_pitch(p[r])};
         R.ph = replica_phys(p[r]);
         R.ref[0] = (float)p[r].rho_ref[0];
         R.ref[1] = (float)p[r].rho_ref[1];
         b->reps.push_back(R);
-        off += align256(2 * (size_t)kQ * R.g.nsites * sizeof(float)) / sizeof(float);
+        off += align256(2 * (size_t)kQ * R.g.pitch * sizeof(float)) / sizeof(float);
     }
     fmlb_status st = FMLB_OK;
     auto fail = [&](fmlb_status s) {

@@ -168,14 +168,14 @@ __device__ __forceinline__ void fused_tile(const StepArgs<L, S> &a, int t0, int 
     const int n0 = g.nx, n1 = D3 ? g.ny : 1, nm = D3 ? g.nz : g.ny;
     const uint32_t s1 = (uint32_t)n0;                          // site stride along plane axis 1
     const uint32_t sm = D3 ? (uint32_t)n0 * n1 : (uint32_t)n0;  // site stride along the march axis
-    const uint32_t pop_bytes = (uint32_t)g.nsites * ES;         // one population array
+    const uint32_t pop_bytes = (uint32_t)g.pitch * ES;         // one population array
 
     __amdgpu_buffer_rsrc_t rsrc[2], rdst[2];
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-        rsrc[s] = __builtin_amdgcn_make_buffer_rsrc((void *)(a.src + (size_t)s * Q * g.nsites), 0,
+        rsrc[s] = __builtin_amdgcn_make_buffer_rsrc((void *)(a.src + (size_t)s * Q * g.pitch), 0,
                                                     (int)(Q * pop_bytes), kBufferWord3);
-        rdst[s] = __builtin_amdgcn_make_buffer_rsrc((void *)(a.dst + (size_t)s * Q * g.nsites), 0,
+        rdst[s] = __builtin_amdgcn_make_buffer_rsrc((void *)(a.dst + (size_t)s * Q * g.pitch), 0,
                                                     (int)(Q * pop_bytes), kBufferWord3);
     }
 
@@ -394,14 +394,14 @@ __device__ __forceinline__ void fused_tile_async(const StepArgs<L, S> &a, int t0
     const int n0 = g.nx, n1 = D3 ? g.ny : 1, nm = D3 ? g.nz : g.ny;
     const uint32_t s1 = (uint32_t)n0;
     const uint32_t sm = D3 ? (uint32_t)n0 * n1 : (uint32_t)n0;
-    const uint32_t pop_bytes = (uint32_t)g.nsites * ES;
+    const uint32_t pop_bytes = (uint32_t)g.pitch * ES;
 
     __amdgpu_buffer_rsrc_t rsrc[2], rdst[2];
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-        rsrc[s] = __builtin_amdgcn_make_buffer_rsrc((void *)(a.src + (size_t)s * Q * g.nsites), 0,
+        rsrc[s] = __builtin_amdgcn_make_buffer_rsrc((void *)(a.src + (size_t)s * Q * g.pitch), 0,
                                                     (int)(Q * pop_bytes), kBufferWord3);
-        rdst[s] = __builtin_amdgcn_make_buffer_rsrc((void *)(a.dst + (size_t)s * Q * g.nsites), 0,
+        rdst[s] = __builtin_amdgcn_make_buffer_rsrc((void *)(a.dst + (size_t)s * Q * g.pitch), 0,
                                                     (int)(Q * pop_bytes), kBufferWord3);
     }
 
@@ -722,14 +722,14 @@ __device__ __forceinline__ void fused_tile_rows_body(const StepArgs<L, S> &a, in
     const int n0 = g.nx, n1 = D3 ? g.ny : 1, nm = D3 ? g.nz : g.ny;
     const uint32_t s1 = (uint32_t)n0;
     const uint32_t sm = D3 ? (uint32_t)n0 * n1 : (uint32_t)n0;
-    const uint32_t pop_bytes = (uint32_t)g.nsites * ES;
+    const uint32_t pop_bytes = (uint32_t)g.pitch * ES;
 
     __amdgpu_buffer_rsrc_t rsrc[2], rdst[2];
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-        rsrc[s] = __builtin_amdgcn_make_buffer_rsrc((void *)(a.src + (size_t)s * Q * g.nsites), 0,
+        rsrc[s] = __builtin_amdgcn_make_buffer_rsrc((void *)(a.src + (size_t)s * Q * g.pitch), 0,
                                                     (int)(Q * pop_bytes), kBufferWord3);
-        rdst[s] = __builtin_amdgcn_make_buffer_rsrc((void *)(a.dst + (size_t)s * Q * g.nsites), 0,
+        rdst[s] = __builtin_amdgcn_make_buffer_rsrc((void *)(a.dst + (size_t)s * Q * g.pitch), 0,
                                                     (int)(Q * pop_bytes), kBufferWord3);
     }
 
@@ -1086,14 +1086,14 @@ bool fused_supported(const Geom &g, int tile_x, int tile_y, int march)
 {
     if (std::is_same<S, double>::value) return false;
     // one species' array must be addressable by a 32-bit buffer offset
-    if ((double)L::Q * (double)g.nsites * (double)sizeof(S) >= 4294967295.0) return false;
+    if ((double)L::Q * (double)g.pitch * (double)sizeof(S) >= 4294967295.0) return false;
     // Any lattice size otherwise: ragged tiles are masked and every plane
     // index wraps periodically (with fewer than 3 planes the ring simply holds
     // copies).
     if (L::D == 3 && tile_x == 256 && g.nx != 256) return false;  // full-width tiles only
     // full-width tiles pull both species through one buffer resource
     if (L::D == 3 && (tile_x == 256 || (tile_x == 0 && g.nx == 256)) &&
-        2.0 * (double)L::Q * (double)g.nsites * (double)sizeof(S) >= 4294967295.0)
+        2.0 * (double)L::Q * (double)g.pitch * (double)sizeof(S) >= 4294967295.0)
         return false;
     return tile_x == 0 || fused_shape_valid<L, S>(tile_x, tile_y, march);
 }

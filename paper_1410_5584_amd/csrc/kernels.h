@@ -46,11 +46,11 @@ struct StepArgs {
 };
 
 template <class L, class S>
-__device__ __forceinline__ typename Storage<S>::Real load_pop(const S *buf, size_t nsites, int s, int i,
+__device__ __forceinline__ typename Storage<S>::Real load_pop(const S *buf, size_t pitch, int s, int i,
                                                               size_t site, typename Storage<S>::Real ref)
 {
     using Real = typename Storage<S>::Real;
-    Real v = Storage<S>::load(buf, ((size_t)(s * L::Q + i)) * nsites + site);
+    Real v = Storage<S>::load(buf, ((size_t)(s * L::Q + i)) * pitch + site);
     if (Storage<S>::deviation) v += Real(L::w36[i]) / Real(36) * ref;
     return v;
 }
@@ -59,18 +59,18 @@ __device__ __forceinline__ typename Storage<S>::Real load_pop(const S *buf, size
 // w_i ref is formed in FP64, then rounded once to the storage format (host
 // I/O and initial states).
 template <class L, class S>
-__device__ __forceinline__ void store_pop_f64(S *buf, size_t nsites, int s, int i, size_t site, double v, double ref)
+__device__ __forceinline__ void store_pop_f64(S *buf, size_t pitch, int s, int i, size_t site, double v, double ref)
 {
     using Real = typename Storage<S>::Real;
     if (Storage<S>::deviation) v -= (double)L::w36[i] / 36.0 * ref;
-    Storage<S>::store(buf, ((size_t)(s * L::Q + i)) * nsites + site, (Real)v);
+    Storage<S>::store(buf, ((size_t)(s * L::Q + i)) * pitch + site, (Real)v);
 }
 
 // Absolute FP64 value of a stored population.
 template <class L, class S>
-__device__ __forceinline__ double load_pop_f64(const S *buf, size_t nsites, int s, int i, size_t site, double ref)
+__device__ __forceinline__ double load_pop_f64(const S *buf, size_t pitch, int s, int i, size_t site, double ref)
 {
-    double v = (double)Storage<S>::load(buf, ((size_t)(s * L::Q + i)) * nsites + site);
+    double v = (double)Storage<S>::load(buf, ((size_t)(s * L::Q + i)) * pitch + site);
     if (Storage<S>::deviation) v += (double)L::w36[i] / 36.0 * ref;
     return v;
 }
@@ -88,7 +88,7 @@ __device__ __forceinline__ void pull_site(const S *src, const Geom &g, int x, in
         const int zs = L::D == 3 ? wrap(z, -L::cz[i], g.nz) : 0;
         const size_t site = (size_t)xs + (size_t)g.nx * ((size_t)ys + (size_t)g.ny * (size_t)zs);
 #pragma unroll
-        for (int s = 0; s < 2; ++s) f[s][i] = load_pop<L, S>(src, g.nsites, s, i, site, ref[s]);
+        for (int s = 0; s < 2; ++s) f[s][i] = load_pop<L, S>(src, g.pitch, s, i, site, ref[s]);
     }
 }
 
@@ -105,7 +105,7 @@ __device__ __forceinline__ void pull_site_stored(const S *src, const Geom &g, in
         const int zs = L::D == 3 ? wrap(z, -L::cz[i], g.nz) : 0;
         const size_t site = (size_t)xs + (size_t)g.nx * ((size_t)ys + (size_t)g.ny * (size_t)zs);
 #pragma unroll
-        for (int s = 0; s < 2; ++s) f[s][i] = Storage<S>::load(src, ((size_t)(s * L::Q + i)) * g.nsites + site);
+        for (int s = 0; s < 2; ++s) f[s][i] = Storage<S>::load(src, ((size_t)(s * L::Q + i)) * g.pitch + site);
     }
 }
 
@@ -159,7 +159,7 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs<L, S> a, uint32_t si
 #pragma unroll
                               for (int i = 0; i < L::Q; ++i)
                               {
-                                  const size_t k = ((size_t)(s * L::Q + i)) * g.nsites + site;
+                                  const size_t k = ((size_t)(s * L::Q + i)) * g.pitch + site;
                                   if constexpr (Storage<S>::stochastic)
                                       Storage<S>::store_sr(a.dst, k, fs[i],
                                                            sr_bits((uint32_t)site + site_off, (uint32_t)(s * L::Q + i), a.step_lo,
@@ -190,7 +190,7 @@ __global__ __launch_bounds__(256) void init_kernel(S *dst, const double *rho, Ge
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
             const double w = (double)L::w36[i] / 36.0;
-            store_pop_f64<L, S>(dst, g.nsites, s, i, site, w * rho[(size_t)s * g.nsites + nsite],
+            store_pop_f64<L, S>(dst, g.pitch, s, i, site, w * rho[(size_t)s * g.nsites + nsite],
                                 (double)(s == 0 ? ref0 : ref1));
         }
     }
@@ -208,7 +208,7 @@ __global__ __launch_bounds__(256) void gather_pop_kernel(const S *src, double *o
     const int xs = wrap(x, -cx, g.nx), ys = wrap(y, -cy, g.ny), zs = L::D == 3 ? wrap(z, -cz, g.nz) : 0;
     const size_t src_site = (size_t)xs + (size_t)g.nx * ((size_t)ys + (size_t)g.ny * (size_t)zs);
     const size_t site = (size_t)x + (size_t)g.nx * ((size_t)y + (size_t)g.ny * (size_t)z);
-    out[site] = load_pop_f64<L, S>(src, g.nsites, s, i, src_site, (double)ref);
+    out[site] = load_pop_f64<L, S>(src, g.pitch, s, i, src_site, (double)ref);
 }
 
 // Inverse of gather_pop_kernel: buf_i(r) = in[r + c_i].
@@ -223,7 +223,7 @@ __global__ __launch_bounds__(256) void scatter_pop_kernel(S *dst, const double *
     const int xn = wrap(x, cx, g.nx), yn = wrap(y, cy, g.ny), zn = L::D == 3 ? wrap(z, cz, g.nz) : 0;
     const size_t nsite = (size_t)xn + (size_t)g.nx * ((size_t)yn + (size_t)g.ny * (size_t)zn);
     const size_t site = (size_t)x + (size_t)g.nx * ((size_t)y + (size_t)g.ny * (size_t)z);
-    store_pop_f64<L, S>(dst, g.nsites, s, i, site, in[nsite], (double)ref);
+    store_pop_f64<L, S>(dst, g.pitch, s, i, site, in[nsite], (double)ref);
 }
 
 // Roofline reference: the pulls and stores of one step with no arithmetic
@@ -242,12 +242,12 @@ __global__ __launch_bounds__(256) void pull_copy_kernel(const S *src, S *dst, Ge
         const int zs = L::D == 3 ? wrap(z, -L::cz[i], g.nz) : 0;
         const size_t s2 = (size_t)xs + (size_t)g.nx * ((size_t)ys + (size_t)g.ny * (size_t)zs);
 #pragma unroll
-        for (int s = 0; s < 2; ++s) v[s][i] = src[((size_t)(s * L::Q + i)) * g.nsites + s2];
+        for (int s = 0; s < 2; ++s) v[s][i] = src[((size_t)(s * L::Q + i)) * g.pitch + s2];
     }
 #pragma unroll
     for (int i = 0; i < L::Q; ++i)
 #pragma unroll
-        for (int s = 0; s < 2; ++s) dst[((size_t)(s * L::Q + i)) * g.nsites + site] = v[s][i];
+        for (int s = 0; s < 2; ++s) dst[((size_t)(s * L::Q + i)) * g.pitch + site] = v[s][i];
 }
 
 // Bandwidth references for the roofline (not part of the method): streaming

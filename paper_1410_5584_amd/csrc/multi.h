@@ -70,7 +70,7 @@ __device__ __forceinline__ void multi_pull(const S *src, const Geom &g, int x, i
         const int zs = L::D == 3 ? wrap(z, -L::cz[i], g.nz) : 0;
         const size_t site = (size_t)xs + (size_t)g.nx * ((size_t)ys + (size_t)g.ny * (size_t)zs);
 #pragma unroll
-        for (int s = 0; s < N; ++s) f[s][i] = Storage<S>::load(src, ((size_t)(s * L::Q + i)) * g.nsites + site);
+        for (int s = 0; s < N; ++s) f[s][i] = Storage<S>::load(src, ((size_t)(s * L::Q + i)) * g.pitch + site);
     }
 }
 
@@ -266,7 +266,7 @@ __device__ __forceinline__ void multi_collide_store(const MultiArgs<S> &a, typen
                                                    [&](int s, auto &fs) {
 #pragma unroll
                                                        for (int i = 0; i < Q; ++i)
-                                                           Storage<S>::store(a.dst, ((size_t)(s * Q + i)) * a.g.nsites + site,
+                                                           Storage<S>::store(a.dst, ((size_t)(s * Q + i)) * a.g.pitch + site,
                                                                              fs[i]);
                                                    });
 }
@@ -506,13 +506,13 @@ __global__ __launch_bounds__(T0 *T1) void multi_async_kernel(MultiArgs<float> a,
 
     const uint32_t s1 = (uint32_t)n0;
     const uint32_t sm = D3 ? (uint32_t)n0 * n1 : (uint32_t)n0;
-    const uint32_t pop_bytes = (uint32_t)g.nsites * 4u;
+    const uint32_t pop_bytes = (uint32_t)g.pitch * 4u;
     __amdgpu_buffer_rsrc_t rsrc[N], rdst[N];
 #pragma unroll
     for (int s = 0; s < N; ++s) {
-        rsrc[s] = __builtin_amdgcn_make_buffer_rsrc((void *)(a.src + (size_t)s * Q * g.nsites), 0, (int)(Q * pop_bytes),
+        rsrc[s] = __builtin_amdgcn_make_buffer_rsrc((void *)(a.src + (size_t)s * Q * g.pitch), 0, (int)(Q * pop_bytes),
                                                     kBufferWord3);
-        rdst[s] = __builtin_amdgcn_make_buffer_rsrc((void *)(a.dst + (size_t)s * Q * g.nsites), 0, (int)(Q * pop_bytes),
+        rdst[s] = __builtin_amdgcn_make_buffer_rsrc((void *)(a.dst + (size_t)s * Q * g.pitch), 0, (int)(Q * pop_bytes),
                                                     kBufferWord3);
     }
 
@@ -685,7 +685,7 @@ __global__ __launch_bounds__(256) void multi_init_kernel(S *dst, const double *r
         const int yn = wrap(y, L::cy[i], g.ny);
         const int zn = L::D == 3 ? wrap(z, L::cz[i], g.nz) : 0;
         const size_t nsite = (size_t)xn + (size_t)g.nx * ((size_t)yn + (size_t)g.ny * (size_t)zn);
-        store_pop_f64<L, S>(dst, g.nsites, s, i, site, (double)L::w36[i] / 36.0 * rho[nsite], ref);
+        store_pop_f64<L, S>(dst, g.pitch, s, i, site, (double)L::w36[i] / 36.0 * rho[nsite], ref);
     }
 }
 
@@ -704,7 +704,7 @@ __global__ __launch_bounds__(256) void multi_moment_kernel(const S *src, double 
         const int ys = wrap(y, -L::cy[i], g.ny);
         const int zs = L::D == 3 ? wrap(z, -L::cz[i], g.nz) : 0;
         const size_t from = (size_t)xs + (size_t)g.nx * ((size_t)ys + (size_t)g.ny * (size_t)zs);
-        const double v = load_pop_f64<L, S>(src, g.nsites, s, i, from, ref);
+        const double v = load_pop_f64<L, S>(src, g.pitch, s, i, from, ref);
         r += v;
         if (L::cx[i]) j[0] += L::cx[i] > 0 ? v : -v;
         if (L::cy[i]) j[1] += L::cy[i] > 0 ? v : -v;
@@ -734,7 +734,7 @@ __global__ __launch_bounds__(256) void multi_sums_kernel(const S *src, double *p
             const int ys = wrap(y, -L::cy[i], g.ny);
             const int zs = L::D == 3 ? wrap(z, -L::cz[i], g.nz) : 0;
             const size_t from = (size_t)xs + (size_t)g.nx * ((size_t)ys + (size_t)g.ny * (size_t)zs);
-            const double f = load_pop_f64<L, S>(src, g.nsites, s, i, from, ref);
+            const double f = load_pop_f64<L, S>(src, g.pitch, s, i, from, ref);
             v[0] += f;
             if (L::cx[i]) v[1] += L::cx[i] > 0 ? f : -f;
             if (L::cy[i]) v[2] += L::cy[i] > 0 ? f : -f;

@@ -353,7 +353,7 @@ fmlb_status fmlb_multi_create(const fmlb_multi_params *p, void *hip_stream, void
     m->pops[1] = dev_buf[1];
     m->scratch = (unsigned char *)dev_buf[2];
     m->lay = multi_layout(p);
-    m->g = Geom{p->nx, p->ny, p->nz, (size_t)p->nx * p->ny * p->nz};
+    m->g = Geom{p->nx, p->ny, p->nz, (size_t)p->nx * p->ny * p->nz, (size_t)p->nx * p->ny * p->nz};
     m->Q = p->lattice == FMLB_D2Q9 ? 9 : 19;
     m->D = p->lattice == FMLB_D2Q9 ? 2 : 3;
     m->N = p->nspecies;

@@ -21,7 +21,7 @@ __device__ __forceinline__ void pull_site_f64(const S *src, const Geom &g, int x
         const int zs = L::D == 3 ? wrap(z, -L::cz[i], g.nz) : 0;
         const size_t site = (size_t)xs + (size_t)g.nx * ((size_t)ys + (size_t)g.ny * (size_t)zs);
 #pragma unroll
-        for (int s = 0; s < 2; ++s) f[s][i] = load_pop_f64<L, S>(src, g.nsites, s, i, site, (double)ref[s]);
+        for (int s = 0; s < 2; ++s) f[s][i] = load_pop_f64<L, S>(src, g.pitch, s, i, site, (double)ref[s]);
     }
 }
 

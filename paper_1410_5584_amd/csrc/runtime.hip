@@ -414,7 +414,7 @@ fmlb_status fmlb_create(const fmlb_params *p, void *hip_stream, void *const dev_
     c->pops[1] = dev_buf[1];
     c->scratch = reinterpret_cast<unsigned char *>(dev_buf[2]);
     c->lay = scratch_layout(p);
-    c->g = Geom{p->nx, p->ny, p->nz, (size_t)p->nx * p->ny * p->nz};
+    c->g = Geom{p->nx, p->ny, p->nz, (size_t)p->nx * p->ny * p->nz, (size_t)p->nx * p->ny * p->nz};
     c->Q = lattice_q(p->lattice);
     c->D = lattice_d(p->lattice);
     c->cur = 0;
@@ -591,7 +591,8 @@ fmlb_status fmlb_sk_accumulate_static(const fmlb_params *p, const void *pops, do
 {
     if (!p || !pops || !acc) return FMLB_E_NULL;
     if (!valid_params(p)) return FMLB_E_INVALID;
-    const Geom g{p->nx, p->ny, p->nz, (size_t)p->nx * p->ny * p->nz};
+    const size_t nsites = (size_t)p->nx * p->ny * p->nz;
+    const Geom g{p->nx, p->ny, p->nz, nsites, nsites};
     if (g.nsites > (size_t)FMLB_SK_STATIC_MAX_SITES) return FMLB_E_SIZE;
     if (g.nx > kMaxLine || g.ny > kMaxLine || g.nz > kMaxLine) return FMLB_E_UNSUPPORTED;
     void *base = nullptr;

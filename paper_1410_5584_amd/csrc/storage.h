@@ -151,6 +151,12 @@ struct Storage<f16_sr> {
 struct Geom {
     int nx, ny, nz;
     size_t nsites;  // nx * ny * nz
+    size_t pitch;   // elements from one population array to the next (>= nsites)
+    Geom() = default;
+    __host__ __device__ constexpr Geom(int x, int y, int z, size_t n, size_t p)
+        : nx(x), ny(y), nz(z), nsites(n), pitch(p)
+    {
+    }
 };
 
 // r + d with periodic wrap for |d| <= 1.

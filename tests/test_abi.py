@@ -85,8 +85,9 @@ def _rep(fm, **kw):
 def test_batch_required_bytes(fm):
     reps = [_rep(fm, nx=40, ny=33), _rep(fm, nx=256, ny=256), _rep(fm, nx=1, ny=1)]
     a = fm.fmlb_batch_required_bytes(reps, 0)
-    # each replica block 2 x 9 x sites floats, rounded up to 256 bytes
-    want = sum(((2 * 9 * n * 4 + 255) // 256) * 256 for n in (40 * 33, 256 * 256, 1))
+    # each replica block 2 x 9 population arrays of the site count rounded up
+    # to 64 floats (every array starts on a 256-byte boundary)
+    want = sum(2 * 9 * ((n + 63) // 64) * 64 * 4 for n in (40 * 33, 256 * 256, 1))
     assert a == want
     assert fm.fmlb_batch_required_bytes(reps, 1) == want
     assert fm.fmlb_batch_required_bytes(reps, 2) > 2 * 256 * 256 * 8
