@@ -211,7 +211,8 @@ def batched(fm, torch, steps: int, warmup: int, plain_steps: int):
             "plain_per_replica": {"value": round(mlups_p, 2), "unit": "MLUPS", "ms_per_step": round(ms_p, 4),
                                   "steps": plain_steps},
             "vs_plain": round(mlups_b / mlups_p, 2),
-            "note": "546 MB per buffer, above the 256 MB last-level cache: a real HBM fraction"}
+            "note": "packed runs of sites per workgroup (autotuned shape in 'tile': 2 = 512 threads); "
+                    "547 MB per buffer, above the 256 MB last-level cache: a real HBM fraction"}
 
 
 def multi_species(fm, torch, steps: int, warmup: int, n: int = 3):
