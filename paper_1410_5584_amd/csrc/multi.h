@@ -14,11 +14,14 @@
 //   The non-momentum modes of species sigma use normals D (N - 1) + sigma NS + ...
 //   and relax as in the binary model (relax_species).
 //
-// Two passes per step: the first pulls every population and writes the
-// interaction potential phi_sigma = sum_s' G_sigma,s' (rho_s' - rho_ref,s')
-// per site (the force needs only differences, sum_i w_i c_i = 0); the second
-// pulls again, collides and stores.  Storage FP64 (absolute) or FP32
-// (deviations from w_i rho_ref, as in the binary FP32 path).
+// Three launch forms with the same arithmetic (so the same bits): two passes
+// (the first pulls every population and writes the interaction potential
+// phi_sigma = sum_s' G_sigma,s' (rho_s' - rho_ref,s') per site -- the force
+// needs only differences, sum_i w_i c_i = 0 -- the second pulls again,
+// collides and stores); a single pass with register pulls; and a single
+// pass with the next plane pulled into LDS while the current one collides
+// (FP32).  Storage FP64 (absolute) or FP32 (deviations from w_i rho_ref, as
+// in the binary FP32 path).
 #pragma once
 
 #include "fused.h"
@@ -450,21 +453,6 @@ __global__ __launch_bounds__(T0 *T1) void multi_fused_kernel(MultiArgs<S> a, int
     }
 }
 
-// Asynchronous single pass (FP32 storage): the tile walk of the form above,
-// with plane m+2's populations going from memory straight into LDS (buffer
-// loads with the LDS destination bit, one 64-lane row per instruction, no
-// registers held while in flight) during the collision of plane m.  Each
-// wave reads back only the rows its own loads wrote, so those rows need
-// only the wave's own counters; the potential ring is the only LDS shared
-// between waves.  Every population is read from memory once per step (the
-// halo rows are the neighbouring tiles' own rows, mostly served by cache)
-// and written once.  The loads of plane m+2 are spread over the iteration
-// by species (a wave has at most 63 vector memory operations in flight,
-// loads and stores together): species 1's tile and halo rows after the
-// force, species sigma+1's once species sigma is collided, ahead of its
-// stores.  After the first row load of an iteration no LDS read follows
-// until the vmcnt(0) at the top of the next one.  Same helpers in the same
-// order as the two-pass form: the same bits.
 // LDS of the asynchronous form (bytes): the potential ring (4 planes of the
 // tile and its halo ring) and one plane of pulled rows for the tile and the
 // halo ring, N Q words per site.
@@ -476,6 +464,21 @@ constexpr size_t multi_async_lds_bytes(int D, int Q, int N, int T0, int T1)
 }
 constexpr size_t kMaxLdsBytes = 160 * 1024;  // per workgroup (gfx950)
 
+// Asynchronous single pass (FP32 storage): the tile walk of the form above,
+// with plane m+2's populations going from memory straight into LDS (buffer
+// loads with the LDS destination bit, one 64-lane row per instruction, no
+// registers held while in flight) during the collision of plane m.  Each
+// wave reads back only the rows its own loads wrote, so those rows need
+// only the wave's own counters; the potential ring is the only LDS shared
+// between waves.  Every population is written once per step and read once
+// for its own tile; the halo rows are the neighbouring tiles' own rows, from
+// the caches while neighbouring tiles march in step.  The loads of plane
+// m+2 are spread over the iteration by species (a wave has at most 63
+// vector memory operations in flight, loads and stores together): species
+// 1's tile and halo rows after the force, species sigma+1's once species
+// sigma is collided, ahead of its stores.  After the first row load of an
+// iteration no LDS read follows until the vmcnt(0) at the top of the next
+// one.  Same helpers in the same order as the two-pass form: the same bits.
 template <class L, int N, int T0, int T1>
 __global__ __launch_bounds__(T0 *T1) void multi_async_kernel(MultiArgs<float> a, int chunk)
 {
