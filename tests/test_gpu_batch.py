@@ -148,9 +148,12 @@ def test_batch_packed_widths_at_the_limit(fm, tile):
     the x wrap, one row up or down): replicas at and beside the widest packed
     width of each block size (128 for 256 threads, 256 for 512), and wider
     ones on the one-row tiles of the same launch, evolve bit for bit as
-    alone."""
+    alone; so do replicas narrower or shorter than a block."""
     _say("case batch packed widths, tile", tile)
     reps = [(w, 6, (0.9, 1.1), 1.0, 0.6, 1e-4, 40 + k) for k, w in enumerate((127, 128, 129, 200, 255, 256, 257))]
+    # and shapes whose runs of sites wrap around the lattice within a block
+    reps += [(1, 50, (1.0, 1.0), 1.0, 0.3, 1e-4, 60), (3, 200, (0.8, 1.2), 0.9, 0.5, 1e-5, 61),
+             (7, 1, (1.0, 1.0), 1.0, 0.2, 1e-4, 62), (255, 2, (0.9, 1.1), 1.0, 0.7, 1e-4, 63)]
     b, ps = _batch(fm, reps)
     b.set_tile(tile, 3)
     b.step(5)
