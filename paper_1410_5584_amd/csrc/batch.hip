@@ -1,8 +1,11 @@
 // Batched replicas: many independent D2Q9 FP32 lattices advanced by one
-// launch per step.  The launch covers a work list of (replica, tile, chunk)
-// items; each item runs the same per-tile code as the single-lattice fused
-// step (fused_tile), with the replica's own geometry, parameters, seed and
-// site numbering, so every replica evolves bit for bit as it would alone.
+// launch per step (two when some replicas are too wide to pack).  The
+// launch covers a work list of items: packed runs of a replica's sites
+// (batch_pack_walk) or one-row tiles (the single-lattice fused_tile_async),
+// each with the replica's own geometry, parameters, seed and site
+// numbering and the single lattice's per-site helpers, so every replica
+// evolves bit for bit as it would alone.  Each replica's population arrays
+// are padded to a multiple of 64 floats (Geom::pitch).
 //
 // The step number lives in device memory and every launch reads it, so a
 // captured HIP graph of several steps can be replayed any number of times:
@@ -275,7 +278,7 @@ __device__ __forceinline__ void batch_pack_walk(const StepArgs<D2Q9, float> &a, 
 
 #pragma unroll 1
     for (long k = 0; k < nblk; ++k) {
-        // Rows of block k+1 have landed.
+        // Block k+1 has landed.
         __builtin_amdgcn_s_waitcnt(kWaitVm0);
         Real nxt[2][Q], rn[2], jn[2][3];
 #pragma unroll
@@ -303,7 +306,7 @@ __device__ __forceinline__ void batch_pack_walk(const StepArgs<D2Q9, float> &a, 
         };
         Real acc[2][3];
         lattice_acceleration<Lt, Real>(nb, a.ph.negG, acc);
-        // Every LDS read of this iteration is done: the row loads of block k+2.
+        // Every LDS read of this iteration is done: the loads of block k+2.
         const bool more = k + 1 < nblk;
         int x2, y2;
         advance(xn, yn, x2, y2);
