@@ -41,7 +41,7 @@ WORKLOAD = dict(lattice="d3q19", nx=256, ny=256, nz=256, tau=(1.0, 1.0), tau_d=1
 C1 = dict(lattice="d2q9", nx=1024, ny=1024, nz=1, tau=(0.8, 1.2), tau_d=1.0, G=0.5, kT=1e-5, seed=1)
 BYTES_PER_SITE = {("d3q19", "f32"): 304, ("d3q19", "bf16"): 152, ("d3q19", "f16"): 152,
                   ("d2q9", "f32"): 144, ("d2q9", "f64"): 288}
-KERNEL_SOURCES = ["collide.h", "rng.h", "fused.h", "kernels.h", "storage.h", "lattice.h"]
+KERNEL_SOURCES = ["collide.h", "rng.h", "fused.h", "kernels.h", "storage.h", "lattice.h", "fused_ilp.hip"]
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "fused_step_d3q19_f32_256cube_traffic.json")
 COPY_BYTES = 2 ** 31
 STEP_KERNEL = "fused_step_kernel<fmlb::D3Q19, float"
@@ -53,6 +53,9 @@ def kernel_hash() -> str:
     for name in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_1410_5584_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
+    # The compiler flags of the step kernel's translation unit shape its code too.
+    from paper_1410_5584_amd import build as _build
+    h.update(repr((_build.FLAGS, _build.SOURCE_FLAGS.get("fused_ilp.hip"))).encode())
     return h.hexdigest()[:16]
 
 

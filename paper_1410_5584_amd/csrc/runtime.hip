@@ -15,13 +15,17 @@
 
 using namespace fmlb;
 
-// BF16 fused steps: instantiated in fused_bf16.hip, which is compiled with
-// its own scheduling strategy.
+// Fused steps instantiated in fused_ilp.hip, which is compiled with its own
+// scheduling strategy (D3Q19 in every storage and rounding, D2Q9 in BF16).
 namespace fmlb {
-extern template hipError_t launch_fused<D2Q9, __hip_bfloat16>(const StepArgs<D2Q9, __hip_bfloat16> &, int, int, int,
-                                                              hipStream_t);
+extern template hipError_t launch_fused<D3Q19, float>(const StepArgs<D3Q19, float> &, int, int, int, hipStream_t);
+extern template hipError_t launch_fused<D3Q19, __half>(const StepArgs<D3Q19, __half> &, int, int, int, hipStream_t);
 extern template hipError_t launch_fused<D3Q19, __hip_bfloat16>(const StepArgs<D3Q19, __hip_bfloat16> &, int, int,
                                                                int, hipStream_t);
+extern template hipError_t launch_fused<D3Q19, f16_sr>(const StepArgs<D3Q19, f16_sr> &, int, int, int, hipStream_t);
+extern template hipError_t launch_fused<D3Q19, bf16_sr>(const StepArgs<D3Q19, bf16_sr> &, int, int, int, hipStream_t);
+extern template hipError_t launch_fused<D2Q9, __hip_bfloat16>(const StepArgs<D2Q9, __hip_bfloat16> &, int, int, int,
+                                                              hipStream_t);
 }  // namespace fmlb
 
 namespace fmlb {
