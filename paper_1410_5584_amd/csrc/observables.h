@@ -283,17 +283,153 @@ __global__ __launch_bounds__(256) void sk_pair_kernel(const S *src, const typena
 
 constexpr int kMaxLine = 2048;  // longest line the transforms accept
 
-// In-place DFT of every line along one axis: X[k] = sum_n x[n] e^{-2 pi i k n / L}.
-// Line l's elements are base(l) + m * stride, m < L, base(l) = (l % inner) *
-// inner_stride + (l / inner) * outer_stride.  A workgroup transforms P
-// lines with consecutive bases (P > 1 needs inner_stride = 1 and inner a
-// multiple of P): element m of its P lines is then P consecutive values, so
-// the loads and stores of a strided axis are contiguous runs instead of
-// scattered 16-byte accesses.  Power-of-two L use a radix-2 Stockham FFT in
-// LDS with the L/2 twiddles e^{-2 pi i t / L} tabulated once (stage h takes
-// twiddle k L/(2h), the same angle -k/h half-turns as a direct evaluation),
-// other lengths a direct sum against an LDS twiddle table.  L <= 2048.
-// Dynamic LDS: (2 P (L + 1) + L / 2) double2.
+__device__ __forceinline__ double2 cadd(double2 a, double2 b)
+{
+    return make_double2(a.x + b.x, a.y + b.y);
+}
+
+__device__ __forceinline__ double2 csub(double2 a, double2 b)
+{
+    return make_double2(a.x - b.x, a.y - b.y);
+}
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b)
+{
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// Four-point DFT in place: v_r <- sum_s v_s (-i)^(r s).
+__device__ __forceinline__ void dft4(double2 v[4])
+{
+    const double2 a0 = cadd(v[0], v[2]), a1 = csub(v[0], v[2]);
+    const double2 b0 = cadd(v[1], v[3]), b1 = csub(v[1], v[3]);
+    v[0] = cadd(a0, b0);
+    v[2] = csub(a0, b0);
+    v[1] = make_double2(a1.x + b1.y, a1.y - b1.x);  // a1 - i b1
+    v[3] = make_double2(a1.x - b1.y, a1.y + b1.x);  // a1 + i b1
+}
+
+// Lines of a power-of-two length L (2 <= L <= 2048): in-place FFT of every
+// line along one axis, X[k] = sum_n x[n] e^{-2 pi i k n / L}, P lines per
+// workgroup of max(64, P L / 4) threads (P L <= 4096).  Line l's elements
+// are base(l) + m * stride as in dft_lines_kernel below, and P > 1 again
+// needs inner_stride = 1 and inner a multiple of P.
+// Mixed-radix Stockham form: a radix-2 pass first when log2 L is odd, then
+// radix-4 passes.  The pass that joins transforms of length h into ones of
+// length R h (h = 1, then times each radix) takes slot t = blk h + k (k < h)
+// of a line, its inputs a[t + s L / R] (s < R), and writes
+//   b[blk R h + k + r h] = sum_s a[t + s L / R] W_{R h}^{s k} W_R^{r s},
+// W_n = e^{-2 pi i / n}; after the last pass the line holds X in natural
+// order.  Each thread owns one radix-4 slot (two radix-2 slots) per pass;
+// the first pass reads the lines from memory, the last writes them back, and
+// the passes between exchange through one LDS copy of the lines.  The
+// twiddles W_L^j, j < L / 2, are tabulated once per workgroup (a quarter from
+// sincospi, the next quarter by the exact rotation W_L^{j + L/4} = -i W_L^j);
+// W_L^{j + L/2} = -W_L^j covers the rest.
+// Dynamic LDS: (P (L + 1) + L / 2) double2.
+template <int P>
+__global__ __launch_bounds__(1024) void fft_lines_kernel(double2 *A, int L, size_t stride, int inner,
+                                                        size_t inner_stride, size_t outer_stride)
+{
+    extern __shared__ double2 lds[];
+    const int LP = L + 1;  // padded line pitch in LDS
+    double2 *a = lds;
+    double2 *tw = lds + P * LP;
+    const size_t line0 = (size_t)blockIdx.x * P;
+    const size_t base = (line0 % (size_t)inner) * inner_stride + (line0 / (size_t)inner) * outer_stride;
+    const int tid = threadIdx.x, nthreads = blockDim.x;
+    const int q = L / 4;  // radix-4 slots per line
+    auto at = [&](int p, int m) -> double2 & { return A[base + (size_t)p + (size_t)m * stride]; };
+    auto twiddle = [&](int j) -> double2 {
+        const int half = L / 2;
+        if (j < half) return tw[j];
+        const double2 w = tw[j - half];
+        return make_double2(-w.x, -w.y);
+    };
+
+    // First pass (h = 1, no twiddles), straight from memory.
+    int h;
+    if ((31 - __clz(L)) & 1) {
+        for (int e = tid; e < P * (L / 2); e += nthreads) {
+            const int p = e % P, t = e / P;
+            const double2 u = at(p, t), v = at(p, t + L / 2);
+            const double2 y0 = cadd(u, v), y1 = csub(u, v);
+            if (L == 2) {
+                at(p, 0) = y0;
+                at(p, 1) = y1;
+            } else {
+                a[p * LP + 2 * t] = y0;
+                a[p * LP + 2 * t + 1] = y1;
+            }
+        }
+        if (L == 2) return;
+        h = 2;
+    } else {
+        if (tid < P * q) {
+            const int p = tid % P, t = tid / P;
+            double2 v[4];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) v[s] = at(p, t + s * q);
+            dft4(v);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                if (L == 4)
+                    at(p, r) = v[r];
+                else
+                    a[p * LP + 4 * t + r] = v[r];
+            }
+        }
+        if (L == 4) return;
+        h = 4;
+    }
+    for (int j = tid; j < L / 4; j += nthreads) {
+        double sn, cs;
+        sincospi(-2.0 * (double)j / (double)L, &sn, &cs);
+        tw[j] = make_double2(cs, sn);
+        tw[j + L / 4] = make_double2(sn, -cs);
+    }
+    __syncthreads();
+
+    // Radix-4 passes through LDS; the last one writes to memory.
+    const bool active = tid < P * q;
+    const int p = active ? tid % P : 0, t = active ? tid / P : 0;
+    for (; h < L; h *= 4) {
+        const bool final_pass = 4 * h == L;
+        double2 v[4];
+        if (active) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) v[s] = a[p * LP + t + s * q];
+        }
+        __syncthreads();
+        if (active) {
+            const int k = t & (h - 1), blk = t / h;
+            const int j = k * (L / (4 * h));
+            v[1] = cmul(v[1], twiddle(j));
+            v[2] = cmul(v[2], twiddle(2 * j));
+            v[3] = cmul(v[3], twiddle(3 * j));
+            dft4(v);
+            const int o = blk * 4 * h + k;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                if (final_pass)
+                    at(p, o + r * h) = v[r];
+                else
+                    a[p * LP + o + r * h] = v[r];
+            }
+        }
+        if (!final_pass) __syncthreads();
+    }
+}
+
+// Lines of any other length: in-place DFT of every line along one axis,
+// X[k] = sum_n x[n] e^{-2 pi i k n / L}, as a direct sum against an LDS
+// twiddle table.  Line l's elements are base(l) + m * stride, m < L,
+// base(l) = (l % inner) * inner_stride + (l / inner) * outer_stride.  A
+// workgroup transforms P lines with consecutive bases (P > 1 needs
+// inner_stride = 1 and inner a multiple of P): element m of its P lines is
+// then P consecutive values, so the loads and stores of a strided axis are
+// contiguous runs instead of scattered 16-byte accesses.  L <= 2048.
+// Dynamic LDS: (P (L + 1) + L) double2.
 template <int P>
 __global__ __launch_bounds__(256) void dft_lines_kernel(double2 *A, int L, size_t stride, int inner,
                                                         size_t inner_stride, size_t outer_stride)
@@ -301,65 +437,31 @@ __global__ __launch_bounds__(256) void dft_lines_kernel(double2 *A, int L, size_
     extern __shared__ double2 lds[];
     const int LP = L + 1;  // padded line pitch in LDS
     double2 *a = lds;
-    double2 *b = lds + P * LP;
-    double2 *tw = lds + 2 * P * LP;
+    double2 *tw = lds + P * LP;
     const size_t line0 = (size_t)blockIdx.x * P;
     const size_t base = (line0 % (size_t)inner) * inner_stride + (line0 / (size_t)inner) * outer_stride;
     for (int e = threadIdx.x; e < P * L; e += blockDim.x) {
         const int p = e % P, m = e / P;
         a[p * LP + m] = A[base + (size_t)p + (size_t)m * stride];
     }
-    if ((L & (L - 1)) == 0) {
-        for (int t = threadIdx.x; t < L / 2; t += blockDim.x) {
-            double sn, cs;
-            sincospi(-2.0 * (double)t / (double)L, &sn, &cs);
-            tw[t] = make_double2(cs, sn);
+    for (int m = threadIdx.x; m < L; m += blockDim.x) {
+        double sn, cs;
+        sincospi(-2.0 * (double)m / (double)L, &sn, &cs);
+        tw[m] = make_double2(cs, sn);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < P * L; e += blockDim.x) {
+        const int p = e % P, k = e / P;
+        double re = 0, im = 0;
+        int idx = 0;
+        for (int n = 0; n < L; ++n) {
+            const double2 x = a[p * LP + n], t = tw[idx];
+            re += x.x * t.x - x.y * t.y;
+            im += x.x * t.y + x.y * t.x;
+            idx += k;
+            if (idx >= L) idx -= L;
         }
-        __syncthreads();
-        // Stockham radix-2: at the stage of half-size h, element pairs (t, t + L/2)
-        // combine into positions of blocks of size 2h.
-        for (int h = 1; h < L; h <<= 1) {
-            const int tstride = L / (2 * h);
-            for (int e = threadIdx.x; e < P * (L / 2); e += blockDim.x) {
-                const int p = e % P, t = e / P;
-                const int k = t % h;  // position within the current block
-                const int blk = t / h;
-                const double2 u = a[p * LP + t];
-                const double2 v = a[p * LP + t + L / 2];
-                const double2 w = tw[k * tstride];
-                const double2 tv = make_double2(v.x * w.x - v.y * w.y, v.x * w.y + v.y * w.x);
-                b[p * LP + blk * 2 * h + k] = make_double2(u.x + tv.x, u.y + tv.y);
-                b[p * LP + blk * 2 * h + k + h] = make_double2(u.x - tv.x, u.y - tv.y);
-            }
-            __syncthreads();
-            double2 *tmp = a;
-            a = b;
-            b = tmp;
-        }
-        for (int e = threadIdx.x; e < P * L; e += blockDim.x) {
-            const int p = e % P, m = e / P;
-            A[base + (size_t)p + (size_t)m * stride] = a[p * LP + m];
-        }
-    } else {
-        for (int m = threadIdx.x; m < L; m += blockDim.x) {
-            double sn, cs;
-            sincospi(-2.0 * (double)m / (double)L, &sn, &cs);
-            b[m] = make_double2(cs, sn);  // twiddle table in the second buffer
-        }
-        __syncthreads();
-        for (int e = threadIdx.x; e < P * L; e += blockDim.x) {
-            const int p = e % P, k = e / P;
-            double re = 0, im = 0;
-            int idx = 0;
-            for (int n = 0; n < L; ++n) {
-                const double2 x = a[p * LP + n], t = b[idx];
-                re += x.x * t.x - x.y * t.y;
-                im += x.x * t.y + x.y * t.x;
-                idx += k;
-                if (idx >= L) idx -= L;
-            }
-            A[base + (size_t)p + (size_t)k * stride] = make_double2(re, im);
-        }
+        A[base + (size_t)p + (size_t)k * stride] = make_double2(re, im);
     }
 }
 

@@ -2,6 +2,7 @@
 // buffer carving, kernel dispatch over (lattice, storage), host transfers.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -253,24 +254,32 @@ fmlb_status sync(fmlb_ctx *c)
     return FMLB_OK;
 }
 
-// Launch the line transforms of one axis, P lines per workgroup.
+// Launch the line transforms of one axis, P lines per workgroup: the FFT for
+// power-of-two lengths, the direct sum for the others.
 template <int P>
 fmlb_status dft_axis(hipStream_t stream, double2 *A, int L, size_t lines, size_t stride, int inner,
                      size_t inner_stride, size_t outer_stride)
 {
-    const size_t lds = (2 * (size_t)P * (L + 1) + (size_t)L / 2) * sizeof(double2);
-    if (lds > 65536)  // more than the default limit; at most 148 KB of the 160 KB LDS
-        HIP_TRY(hipFuncSetAttribute((const void *)dft_lines_kernel<P>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)lds));
-    hipLaunchKernelGGL(dft_lines_kernel<P>, dim3((unsigned)(lines / P)), dim3(256), lds, stream, A, L, stride, inner,
-                       inner_stride, outer_stride);
+    const bool pow2 = (L & (L - 1)) == 0;
+    const void *fn = pow2 ? (const void *)fft_lines_kernel<P> : (const void *)dft_lines_kernel<P>;
+    const size_t lds = ((size_t)P * (L + 1) + (pow2 ? (size_t)L / 2 : (size_t)L)) * sizeof(double2);
+    const unsigned threads = pow2 ? (unsigned)std::max(64, P * L / 4) : 256u;
+    if (lds > 65536)  // more than the default limit
+        HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    if (pow2)
+        hipLaunchKernelGGL(fft_lines_kernel<P>, dim3((unsigned)(lines / P)), dim3(threads), lds, stream, A, L, stride,
+                           inner, inner_stride, outer_stride);
+    else
+        hipLaunchKernelGGL(dft_lines_kernel<P>, dim3((unsigned)(lines / P)), dim3(threads), lds, stream, A, L, stride,
+                           inner, inner_stride, outer_stride);
     LAUNCH_CHECK();
     return FMLB_OK;
 }
 
 // Forward DFT of a complex lattice field along every axis of length > 1.
 // The strided axes (y, z) take several adjacent lines per workgroup (as many
-// as divide nx and fit 148 KB of LDS), so their accesses are contiguous runs.
+// as divide nx, up to 16, within 4096 elements for the FFT or 148 KB of LDS
+// for the direct sum), so their accesses are contiguous runs.
 fmlb_status dft_field(const Geom &g, hipStream_t stream, double2 *A)
 {
     const int dims[3] = {g.nx, g.ny, g.nz};
@@ -297,12 +306,16 @@ fmlb_status dft_field(const Geom &g, hipStream_t stream, double2 *A)
             inner_stride = 1;
             outer_stride = 0;
         }
+        const bool pow2 = (L & (L - 1)) == 0;
         auto fits = [&](int P) {
-            return (ax == 0 ? P == 1 : inner % (size_t)P == 0) &&
-                   (2 * (size_t)P * (L + 1) + (size_t)L / 2) * sizeof(double2) <= 148 * 1024;
+            if (ax == 0 ? P != 1 : inner % (size_t)P != 0) return false;
+            if (pow2) return (size_t)P * L <= 4096;
+            return ((size_t)P * (L + 1) + (size_t)L) * sizeof(double2) <= 148 * 1024;
         };
         fmlb_status st;
-        if (fits(8))
+        if (fits(16))
+            st = dft_axis<16>(stream, A, L, lines, stride, (int)inner, inner_stride, outer_stride);
+        else if (fits(8))
             st = dft_axis<8>(stream, A, L, lines, stride, (int)inner, inner_stride, outer_stride);
         else if (fits(4))
             st = dft_axis<4>(stream, A, L, lines, stride, (int)inner, inner_stride, outer_stride);
