@@ -457,11 +457,26 @@ __device__ __forceinline__ void fused_tile_async(const StepArgs<L, S> &a, int t0
             }
         }
     };
-    // Asynchronous pull of plane m into rows [2Q][len]: this wave's 64-lane slice.
-    auto dma_pull = [&](int q0, int q1, int m, Raw *rows, int len) {
+    // Offsets (in sites) of the source planes m - c_z, c_z = +1, 0, -1, of
+    // plane m's pulls, taken once per plane for all of its row pulls (the
+    // wrap inside each load's offset cost 50-70 scalar instructions per
+    // plane).
+    auto src_planes = [&](int m, uint32_t (&zq)[3]) {
+        zq[0] = (uint32_t)wrapm(m - 1) * sm;
+        zq[1] = (uint32_t)m * sm;
+        zq[2] = (uint32_t)wrapm(m + 1) * sm;
+    };
+    auto pull_off_z = [&](int q0, int q1, const uint32_t (&zq)[3], int i) -> uint32_t {
+        const int x = wrap(q0, -A::c0(i), n0);
+        const int y = D3 ? wrap(q1, -A::c1(i), n1) : 0;
+        return ((uint32_t)x + s1 * (uint32_t)y + zq[1 - A::cm(i)]) * ES;
+    };
+    // Asynchronous pull of plane m (source planes zq) into rows [2Q][len]: this
+    // wave's 64-lane slice.
+    auto dma_pull = [&](int q0, int q1, const uint32_t (&zq)[3], Raw *rows, int len) {
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            const uint32_t voff = pull_off(q0, q1, m, i);
+            const uint32_t voff = pull_off_z(q0, q1, zq, i);
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
                 lds_void_t *dst = (lds_void_t *)(rows + (s * Q + i) * len + wave * 64);
@@ -483,15 +498,15 @@ __device__ __forceinline__ void fused_tile_async(const StepArgs<L, S> &a, int t0
     };
 
     // One species' share of dma_pull.
-    auto dma_pull1 = [&](int s, int q0, int q1, int m, Raw *rows, int len) {
+    auto dma_pull1 = [&](int s, int q0, int q1, const uint32_t (&zq)[3], Raw *rows, int len) {
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             lds_void_t *dst = (lds_void_t *)(rows + (s * Q + i) * len + wave * 64);
             if constexpr (ES == 4)
-                __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc[s], dst, 4, pull_off(q0, q1, m, i), (uint32_t)i * pop_bytes,
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc[s], dst, 4, pull_off_z(q0, q1, zq, i), (uint32_t)i * pop_bytes,
                                                          0, 0);
             else
-                __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc[s], dst, 2, pull_off(q0, q1, m, i), (uint32_t)i * pop_bytes,
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc[s], dst, 2, pull_off_z(q0, q1, zq, i), (uint32_t)i * pop_bytes,
                                                          0, 0);
         }
     };
@@ -533,8 +548,10 @@ __device__ __forceinline__ void fused_tile_async(const StepArgs<L, S> &a, int t0
             }
         }
     }
-    dma_pull(p0, p1, wrapm(mbeg + 1), &own[0][0], NT);
-    if (tid < NHALO) dma_pull(hp0, hp1, wrapm(mbeg + 1), &halo[0][0], NHALO);
+    uint32_t zq1[3];
+    src_planes(wrapm(mbeg + 1), zq1);
+    dma_pull(p0, p1, zq1, &own[0][0], NT);
+    if (tid < NHALO) dma_pull(hp0, hp1, zq1, &halo[0][0], NHALO);
 
 #pragma unroll 1
     for (int m = mbeg; m < mend; ++m) {
@@ -573,14 +590,16 @@ __device__ __forceinline__ void fused_tile_async(const StepArgs<L, S> &a, int t0
         // Every LDS read of this iteration is done: start the row loads of
         // plane m+2 (no LDS read may follow them before the next vmcnt(0)).
         const bool more = m + 2 <= mend;
+        uint32_t zq[3];
+        src_planes(wrapm(m + 2), zq);
         __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
         __builtin_amdgcn_sched_barrier(0);
         if (more) {
             if constexpr (D3) {
-                dma_pull1(0, p0, p1, wrapm(m + 2), &own[0][0], NT);
-                if (tid < NHALO) dma_pull1(0, hp0, hp1, wrapm(m + 2), &halo[0][0], NHALO);
+                dma_pull1(0, p0, p1, zq, &own[0][0], NT);
+                if (tid < NHALO) dma_pull1(0, hp0, hp1, zq, &halo[0][0], NHALO);
             } else {
-                dma_pull(p0, p1, wrapm(m + 2), &own[0][0], NT);
+                dma_pull(p0, p1, zq, &own[0][0], NT);
             }
         }
         __builtin_amdgcn_sched_barrier(0);
@@ -591,8 +610,8 @@ __device__ __forceinline__ void fused_tile_async(const StepArgs<L, S> &a, int t0
                 if (s == 0) {
                     __builtin_amdgcn_sched_barrier(0);
                     if (more) {
-                        dma_pull1(1, p0, p1, wrapm(m + 2), &own[0][0], NT);
-                        if (tid < NHALO) dma_pull1(1, hp0, hp1, wrapm(m + 2), &halo[0][0], NHALO);
+                        dma_pull1(1, p0, p1, zq, &own[0][0], NT);
+                        if (tid < NHALO) dma_pull1(1, hp0, hp1, zq, &halo[0][0], NHALO);
                     }
                     __builtin_amdgcn_sched_barrier(0);
                 }
@@ -608,7 +627,7 @@ __device__ __forceinline__ void fused_tile_async(const StepArgs<L, S> &a, int t0
             if constexpr (!D3) {
                 if (s == 0 && more && tid < NHALO) {
                     __builtin_amdgcn_sched_barrier(0);
-                    dma_pull(hp0, hp1, wrapm(m + 2), &halo[0][0], NHALO);
+                    dma_pull(hp0, hp1, zq, &halo[0][0], NHALO);
                     __builtin_amdgcn_sched_barrier(0);
                 }
             }
@@ -861,6 +880,26 @@ __device__ __forceinline__ void fused_tile_rows_body(const StepArgs<L, S> &a, in
                 w[s][i] = __builtin_amdgcn_raw_buffer_load_b16(rsrc[s], pull_off(q0, q1, m, i), (uint32_t)i * pop_bytes, 0);
         }
     };
+    // 16-bit halo pulls take the offsets (in sites) of the source planes
+    // m - c_z, c_z = +1, 0, -1, once per plane for both species: wrapping the
+    // plane inside each load's offset (pull1) cost about 45 scalar
+    // instructions per species, and these steps are bound by instruction
+    // issue (256^3: BF16 0.794 -> 0.745 ms, FP16 0.792 -> 0.758).  FP32 keeps
+    // pull1: with the shared offsets it ran 1.012 -> 1.049 ms.
+    auto src_planes = [&](int m, uint32_t (&zq)[3]) {
+        zq[0] = (uint32_t)wrapm(m - 1) * sm;
+        zq[1] = (uint32_t)m * sm;
+        zq[2] = (uint32_t)wrapm(m + 1) * sm;
+    };
+    auto pull1z = [&](int s, int q0, int q1, const uint32_t (&zq)[3], HaloWord (&w)[2][Q]) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int x = wrap(q0, -A::c0(i), n0);
+            const int y = D3 ? wrap(q1, -A::c1(i), n1) : 0;
+            const uint32_t voff = ((uint32_t)x + s1 * (uint32_t)y + zq[1 - A::cm(i)]) * ES;
+            w[s][i] = __builtin_amdgcn_raw_buffer_load_b16(rsrc[s], voff, (uint32_t)i * pop_bytes, 0);
+        }
+    };
 
     // Issue schedule of one plane (per thread: 38 row loads into LDS, 38
     // halo loads into registers, 38 stores).  A wave can have at most 63
@@ -944,7 +983,13 @@ __device__ __forceinline__ void fused_tile_rows_body(const StepArgs<L, S> &a, in
             }
             put_ring(ring[slot(m + 1)][s], hb, hx, r);
         }
-        if (m + 2 <= mend) pull1(0, hp0, hp1, wrapm(m + 2), hn);
+        uint32_t zq[3];
+        if constexpr (ES == 4) {
+            if (m + 2 <= mend) pull1(0, hp0, hp1, wrapm(m + 2), hn);
+        } else {
+            src_planes(wrapm(m + 2), zq);
+            if (m + 2 <= mend) pull1z(0, hp0, hp1, zq, hn);
+        }
         // Workgroup barrier for the density ring only: the ring writes are
         // complete once lgkmcnt drains (no row loads are in flight here).
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
@@ -962,7 +1007,11 @@ __device__ __forceinline__ void fused_tile_rows_body(const StepArgs<L, S> &a, in
         const bool more = m + 2 <= mend;
         __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
         __builtin_amdgcn_sched_barrier(0);
-        if (more) pull1(1, hp0, hp1, wrapm(m + 2), hn);
+        if constexpr (ES == 4) {
+            if (more) pull1(1, hp0, hp1, wrapm(m + 2), hn);
+        } else {
+            if (more) pull1z(1, hp0, hp1, zq, hn);
+        }
         __builtin_amdgcn_sched_barrier(0);
         const uint32_t site = (uint32_t)p0 + s1 * (uint32_t)(D3 ? p1 : 0) + sm * (uint32_t)m;
         const uint32_t voff = site * ES;
