@@ -197,9 +197,10 @@ fmlb_status fmlb_sk_get(fmlb_ctx *ctx, int which, double *out, int64_t *n_sample
 
 /* For callers that cannot allocate device memory or call an allocator (code
  * under HIP graph capture, allocation-free serving loops): the accumulation
- * of fmlb_sk_accumulate without a context.  The work arrays (32 bytes per
- * site) live in a static device array of the library, one per GPU, of
- * FMLB_SK_STATIC_MAX_SITES * 32 bytes (32 MiB), held until the process ends.
+ * of fmlb_sk_accumulate without a context.  The work arrays (the FP64
+ * moments of both species and one complex FP64 field: 80 bytes per site)
+ * live in a static device array of the library, one per GPU, of
+ * FMLB_SK_STATIC_MAX_SITES * 80 bytes (80 MiB), held until the process ends.
  *   p:    the lattice, storage and rho_ref of the state (validated as by
  *         fmlb_create).
  *   pops: device, the stored state as a context keeps it (pull layout,

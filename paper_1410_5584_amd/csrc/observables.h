@@ -211,7 +211,9 @@ __global__ __launch_bounds__(kRedBlock) void health_kernel(const S *src, double 
 // Pairs: 0 (rho_1, rho_2); 1 + alpha (j_bar_1,alpha, j_bar_2,alpha);
 // D + 1 the physical barycentric velocity (v_b,x, v_b,y) and, in 3D, D + 2
 // (v_b,z, 0), with v_b = (j_bar_1 + j_bar_2 + (F_1 + F_2) / 2) / rho_t and
-// the force of Eq. (87) from the density buffer rho[2][sites].
+// the force of Eq. (87) at the same time level.  The populations are pulled
+// once per snapshot (sk_moments_kernel); every pair's field is then built
+// from those moments (sk_field_kernel).
 // ---------------------------------------------------------------------------
 template <class L>
 constexpr int sk_pairs()
@@ -219,15 +221,19 @@ constexpr int sk_pairs()
     return L::D == 2 ? 4 : 6;
 }
 
+// Moments of both species, pulled once per snapshot, in FP64:
+// mom[q][sites] = rho_q (q = 0, 1) and mom[2 + q D + alpha][sites] =
+// j_bar_q,alpha, each summed in velocity order.
 template <class L, class S>
-__global__ __launch_bounds__(256) void sk_pair_kernel(const S *src, const typename Storage<S>::Real *rho, double2 *Z,
-                                                      Geom g, int pair, double negG, typename Storage<S>::Real ref0,
-                                                      typename Storage<S>::Real ref1)
+__global__ __launch_bounds__(256) void sk_moments_kernel(const S *src, double *mom, Geom g,
+                                                         typename Storage<S>::Real ref0,
+                                                         typename Storage<S>::Real ref1)
 {
     using Real = typename Storage<S>::Real;
     const Real ref[2] = {ref0, ref1};
     constexpr int D = L::D;
-    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < g.nsites; t += (size_t)gridDim.x * blockDim.x) {
+    const size_t n = g.nsites;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
         int x, y, z;
         site_xyz(t, g, x, y, z);
         double f[2][L::Q];
@@ -242,15 +248,33 @@ __global__ __launch_bounds__(256) void sk_pair_kernel(const S *src, const typena
                 if (L::cy[i]) j[q][1] += L::cy[i] > 0 ? f[q][i] : -f[q][i];
                 if (D == 3 && L::cz[i]) j[q][2] += L::cz[i] > 0 ? f[q][i] : -f[q][i];
             }
-        double X = 0, Y = 0;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            mom[(size_t)q * n + t] = r[q];
+#pragma unroll
+            for (int al = 0; al < D; ++al) mom[(size_t)(2 + q * D + al) * n + t] = j[q][al];
+        }
+    }
+}
+
+// Field of pair `pair` from the moments: Z[t] = X + iY.
+template <class L>
+__global__ __launch_bounds__(256) void sk_field_kernel(const double *mom, double2 *Z, Geom g, int pair, double negG)
+{
+    constexpr int D = L::D;
+    const size_t n = g.nsites;
+    for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
+        double X, Y;
         if (pair == 0) {
-            X = r[0];
-            Y = r[1];
+            X = mom[t];
+            Y = mom[n + t];
         } else if (pair <= D) {
-            X = j[0][pair - 1];
-            Y = j[1][pair - 1];
+            X = mom[(size_t)(2 + pair - 1) * n + t];
+            Y = mom[(size_t)(2 + D + pair - 1) * n + t];
         } else {
             // barycentric velocity components al0 (real part) and al0 + 1 (imaginary part, if any)
+            int x, y, z;
+            site_xyz(t, g, x, y, z);
             const int al0 = 2 * (pair - D - 1);
             double a[2][3] = {{0, 0, 0}, {0, 0, 0}};
 #pragma unroll
@@ -261,18 +285,20 @@ __global__ __launch_bounds__(256) void sk_pair_kernel(const S *src, const typena
                 const double w = (double)L::w36[i] / 36.0;
 #pragma unroll
                 for (int q = 0; q < 2; ++q) {
-                    const double ro = (double)rho[(size_t)(1 - q) * g.nsites + nsite];
+                    const double ro = mom[(size_t)(1 - q) * n + nsite];
                     a[q][0] += L::cx[i] * w * ro;
                     a[q][1] += L::cy[i] * w * ro;
                     a[q][2] += L::cz[i] * w * ro;
                 }
             }
-            const double rt = r[0] + r[1];
-            double vb[3];
+            const double r0 = mom[t], r1 = mom[n + t];
+            const double rt = r0 + r1;
+            double vb[3] = {0, 0, 0};
 #pragma unroll
-            for (int al = 0; al < 3; ++al) {
-                const double Ft = negG * (r[0] * a[0][al] + r[1] * a[1][al]);
-                vb[al] = rt > 0 ? (j[0][al] + j[1][al] + 0.5 * Ft) / rt : 0.0;
+            for (int al = 0; al < D; ++al) {
+                const double Ft = negG * (r0 * a[0][al] + r1 * a[1][al]);
+                const double jt = mom[(size_t)(2 + al) * n + t] + mom[(size_t)(2 + D + al) * n + t];
+                vb[al] = rt > 0 ? (jt + 0.5 * Ft) / rt : 0.0;
             }
             X = vb[al0];
             Y = al0 + 1 < D ? vb[al0 + 1] : 0.0;

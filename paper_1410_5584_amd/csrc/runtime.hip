@@ -65,6 +65,10 @@ size_t real_size(int storage) { return storage == FMLB_F64 ? 8 : 4; }
 
 constexpr int kReduceBlocks = 1024;
 constexpr int kSkQuantities = 7;
+// FP64 moments per site of the structure-factor work arrays: rho_1, rho_2
+// and the D components of j_bar_1 and j_bar_2 (kSkMoments for D = 3).
+constexpr int kSkMoments = 2 + 2 * 3;
+int sk_moments(int lattice) { return lattice == FMLB_D2Q9 ? 2 + 2 * 2 : kSkMoments; }
 
 bool valid_params(const fmlb_params *p)
 {
@@ -86,7 +90,7 @@ bool valid_params(const fmlb_params *p)
 }
 
 struct Layout {
-    size_t rho, stage, skA, skacc, partial, modeacc, misc, total;
+    size_t rho, stage, skA, skmom, skacc, partial, modeacc, misc, total;
 };
 
 Layout scratch_layout(const fmlb_params *p)
@@ -101,6 +105,8 @@ Layout scratch_layout(const fmlb_params *p)
     o += align256(2 * n * sizeof(double));
     l.skA = o;
     o += align256(n * 2 * sizeof(double));
+    l.skmom = o;
+    o += align256((size_t)sk_moments(p->lattice) * n * sizeof(double));
     l.skacc = o;
     o += align256((size_t)kSkQuantities * n * sizeof(double));
     l.partial = o;
@@ -331,32 +337,29 @@ fmlb_status dft_field(const Geom &g, hipStream_t stream, double2 *A)
 // Bytes of work arrays the structure-factor accumulation needs per site:
 // the densities of both species (FP64 at most, for the force in v_b) and one
 // complex FP64 field.
-constexpr size_t kSkWorkBytesPerSite = 2 * sizeof(double) + sizeof(double2);
+// Bytes of work arrays the structure-factor accumulation needs per site: the
+// FP64 moments of both species (2 + 2 D values; D = 3 at most) and one
+// complex FP64 field.
+constexpr size_t kSkWorkBytesPerSite = kSkMoments * sizeof(double) + sizeof(double2);
 
 // The structure-factor accumulation of one snapshot (Sec. VI A): the seven
 // quantities of fmlb_sk_accumulate are added to acc[7][sites], two real
-// fields per complex transform.  rho and Z are work arrays of 2 * sites
-// Real and sites double2.
+// fields per complex transform.  mom and Z are work arrays of (2 + 2 D) *
+// sites doubles and sites double2.
 template <class L, class S>
-fmlb_status sk_accumulate_impl(const fmlb_params &p, const Geom &g, hipStream_t stream, const S *src,
-                               typename Storage<S>::Real *rho, double2 *Z, double *acc)
+fmlb_status sk_accumulate_impl(const fmlb_params &p, const Geom &g, hipStream_t stream, const S *src, double *mom,
+                               double2 *Z, double *acc)
 {
     using Real = typename Storage<S>::Real;
     const size_t n = g.nsites;
     constexpr int D = L::D;
-    const Real ref0 = (Real)p.rho_ref[0], ref1 = (Real)p.rho_ref[1];
-    StepArgs<L, S> a{};
-    a.src = src;
-    a.rho = rho;
-    a.g = g;
-    const SiteGrid sg = site_grid(g);
-    hipLaunchKernelGGL((density_kernel<L, S>), sg.grid, sg.block, 0, stream, a);
-    LAUNCH_CHECK();
     const dim3 gb(stride_blocks(n)), tb(256);
+    hipLaunchKernelGGL((sk_moments_kernel<L, S>), gb, tb, 0, stream, src, mom, g, (Real)p.rho_ref[0],
+                       (Real)p.rho_ref[1]);
+    LAUNCH_CHECK();
     const double inv_n = 1.0 / (double)n;
     for (int pair = 0; pair < sk_pairs<L>(); ++pair) {
-        hipLaunchKernelGGL((sk_pair_kernel<L, S>), gb, tb, 0, stream, src, (const Real *)rho, Z, g, pair, -p.G, ref0,
-                           ref1);
+        hipLaunchKernelGGL((sk_field_kernel<L>), gb, tb, 0, stream, (const double *)mom, Z, g, pair, -p.G);
         LAUNCH_CHECK();
         if (fmlb_status st = dft_field(g, stream, Z)) return st;
         const int kind = pair == 0 ? 0 : (pair <= D ? 1 : 2);
@@ -595,9 +598,8 @@ fmlb_status fmlb_sk_accumulate(fmlb_ctx *c)
     fmlb_status st = dispatch(c, [&](auto l, auto sp) -> fmlb_status {
         using L = decltype(l);
         using S = std::remove_pointer_t<decltype(sp)>;
-        using Real = typename Storage<S>::Real;
         return sk_accumulate_impl<L, S>(c->p, c->g, c->stream, reinterpret_cast<const S *>(c->pops[c->cur]),
-                                        scr<Real>(c, c->lay.rho), Z, acc);
+                                        scr<double>(c, c->lay.skmom), Z, acc);
     });
     if (st) return st;
     c->sk_samples += 1;
@@ -614,17 +616,16 @@ fmlb_status fmlb_sk_accumulate_static(const fmlb_params *p, const void *pops, do
     if (g.nx > kMaxLine || g.ny > kMaxLine || g.nz > kMaxLine) return FMLB_E_UNSUPPORTED;
     void *base = nullptr;
     if (fmlb_status st = static_scratch(&base)) return st;
-    // work arrays carved from the static array: rho (2 sites x 8 bytes), Z
+    // work arrays carved from the static array: the moments, then Z
     unsigned char *w = reinterpret_cast<unsigned char *>(base);
-    double2 *Z = reinterpret_cast<double2 *>(w + 2 * g.nsites * sizeof(double));
+    double2 *Z = reinterpret_cast<double2 *>(w + (size_t)sk_moments(p->lattice) * g.nsites * sizeof(double));
     fmlb_ctx tmp{};
     tmp.p = *p;
     return dispatch(&tmp, [&](auto l, auto sp) -> fmlb_status {
         using L = decltype(l);
         using S = std::remove_pointer_t<decltype(sp)>;
-        using Real = typename Storage<S>::Real;
         return sk_accumulate_impl<L, S>(*p, g, reinterpret_cast<hipStream_t>(hip_stream),
-                                        reinterpret_cast<const S *>(pops), reinterpret_cast<Real *>(w), Z, acc);
+                                        reinterpret_cast<const S *>(pops), reinterpret_cast<double *>(w), Z, acc);
     });
 }
 
