@@ -257,9 +257,12 @@ __global__ __launch_bounds__(256) void sk_moments_kernel(const S *src, double *m
     }
 }
 
-// Field of pair `pair` from the moments: Z[t] = X + iY.
+// Field of pair `pair` from the moments: Z[t] = X + iY.  In 3D the pass of
+// pair D + 1 (v_b,x, v_b,y) also keeps v_b,z in the slot of j_bar_1,x, which
+// no later pair reads, and pair D + 2 (v_b,z, 0) takes it from there instead
+// of gathering the force's neighbour densities again.
 template <class L>
-__global__ __launch_bounds__(256) void sk_field_kernel(const double *mom, double2 *Z, Geom g, int pair, double negG)
+__global__ __launch_bounds__(256) void sk_field_kernel(double *mom, double2 *Z, Geom g, int pair, double negG)
 {
     constexpr int D = L::D;
     const size_t n = g.nsites;
@@ -271,11 +274,13 @@ __global__ __launch_bounds__(256) void sk_field_kernel(const double *mom, double
         } else if (pair <= D) {
             X = mom[(size_t)(2 + pair - 1) * n + t];
             Y = mom[(size_t)(2 + D + pair - 1) * n + t];
+        } else if (pair == D + 2) {
+            X = mom[2 * n + t];
+            Y = 0.0;
         } else {
-            // barycentric velocity components al0 (real part) and al0 + 1 (imaginary part, if any)
+            // the barycentric velocity: components x (real part) and y (imaginary part)
             int x, y, z;
             site_xyz(t, g, x, y, z);
-            const int al0 = 2 * (pair - D - 1);
             double a[2][3] = {{0, 0, 0}, {0, 0, 0}};
 #pragma unroll
             for (int i = 1; i < L::Q; ++i) {
@@ -300,8 +305,9 @@ __global__ __launch_bounds__(256) void sk_field_kernel(const double *mom, double
                 const double jt = mom[(size_t)(2 + al) * n + t] + mom[(size_t)(2 + D + al) * n + t];
                 vb[al] = rt > 0 ? (jt + 0.5 * Ft) / rt : 0.0;
             }
-            X = vb[al0];
-            Y = al0 + 1 < D ? vb[al0 + 1] : 0.0;
+            X = vb[0];
+            Y = vb[1];
+            if (D == 3) mom[2 * n + t] = vb[2];
         }
         Z[t] = make_double2(X, Y);
     }

@@ -359,7 +359,7 @@ fmlb_status sk_accumulate_impl(const fmlb_params &p, const Geom &g, hipStream_t 
     LAUNCH_CHECK();
     const double inv_n = 1.0 / (double)n;
     for (int pair = 0; pair < sk_pairs<L>(); ++pair) {
-        hipLaunchKernelGGL((sk_field_kernel<L>), gb, tb, 0, stream, (const double *)mom, Z, g, pair, -p.G);
+        hipLaunchKernelGGL((sk_field_kernel<L>), gb, tb, 0, stream, mom, Z, g, pair, -p.G);
         LAUNCH_CHECK();
         if (fmlb_status st = dft_field(g, stream, Z)) return st;
         const int kind = pair == 0 ? 0 : (pair <= D ? 1 : 2);
