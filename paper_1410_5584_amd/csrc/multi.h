@@ -526,6 +526,15 @@ __global__ __launch_bounds__(T0 *T1) void multi_async_kernel(MultiArgs<float> a,
     const bool inside = p0raw < n0 && p1raw < n1;
     const int p0 = p0raw % n0, p1 = p1raw % n1;
     const int box_own = (l1 + OFF1) * H0 + (l0 + 1);
+    // Copies of the wave number and the population stride that the plane loop
+    // marks as changed (three species and more): the LDS destinations and the
+    // population offsets of the row pulls are then recomputed each plane (one
+    // scalar instruction each) instead of being held across the loop, where
+    // they did not fit the scalar registers and came back from VGPR lanes
+    // (three species: 133 v_readlane per plane; 2.129 -> 2.110 ms at 256^3,
+    // four 2.928 -> 2.887; two species ran slower with it, 1.176 -> 1.190).
+    int wave_v = wave;
+    uint32_t popb_v = pop_bytes;
     // halo ring: the rows / columns around the tile, one site per thread
     int hb = -1, hp0 = 0, hp1 = 0;
     if (tid < NHALO) {
@@ -571,8 +580,8 @@ __global__ __launch_bounds__(T0 *T1) void multi_async_kernel(MultiArgs<float> a,
     auto dma1 = [&](int s, int q0, int q1, int m, Raw *rows, int len) __attribute__((always_inline)) {
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            lds_void_t *dst = (lds_void_t *)(rows + (s * Q + i) * len + wave * 64);
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc[s], dst, 4, pull_off(q0, q1, m, i), (uint32_t)i * pop_bytes, 0,
+            lds_void_t *dst = (lds_void_t *)(rows + (s * Q + i) * len + wave_v * 64);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rsrc[s], dst, 4, pull_off(q0, q1, m, i), (uint32_t)i * popb_v, 0,
                                                      0);
         }
     };
@@ -618,6 +627,7 @@ __global__ __launch_bounds__(T0 *T1) void multi_async_kernel(MultiArgs<float> a,
 
 #pragma unroll 1
     for (int m = mbeg; m < mend; ++m) {
+        if constexpr (N >= 3) asm volatile("" : "+s"(wave_v), "+s"(popb_v));
         // Rows of plane m+1 have landed.
         __builtin_amdgcn_s_waitcnt(kWaitVm0);
         Real nxt[N][Q];
@@ -664,7 +674,7 @@ __global__ __launch_bounds__(T0 *T1) void multi_async_kernel(MultiArgs<float> a,
                 }
                 if (inside) {
 #pragma unroll
-                    for (int i = 0; i < Q; ++i) BufIO<float>::store(fs[i], rdst[s], voff, (uint32_t)i * pop_bytes);
+                    for (int i = 0; i < Q; ++i) BufIO<float>::store(fs[i], rdst[s], voff, (uint32_t)i * popb_v);
                 }
             });
 #pragma unroll
