@@ -358,10 +358,13 @@ __device__ __forceinline__ void dft4(double2 v[4])
 // twiddles W_L^j, j < L / 2, are tabulated once per workgroup (a quarter from
 // sincospi, the next quarter by the exact rotation W_L^{j + L/4} = -i W_L^j);
 // W_L^{j + L/2} = -W_L^j covers the rest.
+// With re non-null the input of the first pass is re + i im (two real fields
+// of the same layout) instead of A; the result goes to A either way.
 // Dynamic LDS: (P (L + 1) + L / 2) double2.
 template <int P>
 __global__ __launch_bounds__(1024) void fft_lines_kernel(double2 *A, int L, size_t stride, int inner,
-                                                        size_t inner_stride, size_t outer_stride)
+                                                        size_t inner_stride, size_t outer_stride, const double *re,
+                                                        const double *im)
 {
     extern __shared__ double2 lds[];
     const int LP = L + 1;  // padded line pitch in LDS
@@ -372,6 +375,10 @@ __global__ __launch_bounds__(1024) void fft_lines_kernel(double2 *A, int L, size
     const int tid = threadIdx.x, nthreads = blockDim.x;
     const int q = L / 4;  // radix-4 slots per line
     auto at = [&](int p, int m) -> double2 & { return A[base + (size_t)p + (size_t)m * stride]; };
+    auto in = [&](int p, int m) -> double2 {
+        const size_t k = base + (size_t)p + (size_t)m * stride;
+        return re ? make_double2(re[k], im[k]) : A[k];
+    };
     auto twiddle = [&](int j) -> double2 {
         const int half = L / 2;
         if (j < half) return tw[j];
@@ -384,7 +391,7 @@ __global__ __launch_bounds__(1024) void fft_lines_kernel(double2 *A, int L, size
     if ((31 - __clz(L)) & 1) {
         for (int e = tid; e < P * (L / 2); e += nthreads) {
             const int p = e % P, t = e / P;
-            const double2 u = at(p, t), v = at(p, t + L / 2);
+            const double2 u = in(p, t), v = in(p, t + L / 2);
             const double2 y0 = cadd(u, v), y1 = csub(u, v);
             if (L == 2) {
                 at(p, 0) = y0;
@@ -401,7 +408,7 @@ __global__ __launch_bounds__(1024) void fft_lines_kernel(double2 *A, int L, size
             const int p = tid % P, t = tid / P;
             double2 v[4];
 #pragma unroll
-            for (int s = 0; s < 4; ++s) v[s] = at(p, t + s * q);
+            for (int s = 0; s < 4; ++s) v[s] = in(p, t + s * q);
             dft4(v);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -460,11 +467,13 @@ __global__ __launch_bounds__(1024) void fft_lines_kernel(double2 *A, int L, size
 // workgroup transforms P lines with consecutive bases (P > 1 needs
 // inner_stride = 1 and inner a multiple of P): element m of its P lines is
 // then P consecutive values, so the loads and stores of a strided axis are
-// contiguous runs instead of scattered 16-byte accesses.  L <= 2048.
+// contiguous runs instead of scattered 16-byte accesses.  L <= 2048.  re,
+// im as for fft_lines_kernel.
 // Dynamic LDS: (P (L + 1) + L) double2.
 template <int P>
 __global__ __launch_bounds__(256) void dft_lines_kernel(double2 *A, int L, size_t stride, int inner,
-                                                        size_t inner_stride, size_t outer_stride)
+                                                        size_t inner_stride, size_t outer_stride, const double *re,
+                                                        const double *im)
 {
     extern __shared__ double2 lds[];
     const int LP = L + 1;  // padded line pitch in LDS
@@ -474,7 +483,8 @@ __global__ __launch_bounds__(256) void dft_lines_kernel(double2 *A, int L, size_
     const size_t base = (line0 % (size_t)inner) * inner_stride + (line0 / (size_t)inner) * outer_stride;
     for (int e = threadIdx.x; e < P * L; e += blockDim.x) {
         const int p = e % P, m = e / P;
-        a[p * LP + m] = A[base + (size_t)p + (size_t)m * stride];
+        const size_t k = base + (size_t)p + (size_t)m * stride;
+        a[p * LP + m] = re ? make_double2(re[k], im[k]) : A[k];
     }
     for (int m = threadIdx.x; m < L; m += blockDim.x) {
         double sn, cs;

@@ -264,7 +264,7 @@ fmlb_status sync(fmlb_ctx *c)
 // power-of-two lengths, the direct sum for the others.
 template <int P>
 fmlb_status dft_axis(hipStream_t stream, double2 *A, int L, size_t lines, size_t stride, int inner,
-                     size_t inner_stride, size_t outer_stride)
+                     size_t inner_stride, size_t outer_stride, const double *re, const double *im)
 {
     const bool pow2 = (L & (L - 1)) == 0;
     const void *fn = pow2 ? (const void *)fft_lines_kernel<P> : (const void *)dft_lines_kernel<P>;
@@ -274,10 +274,10 @@ fmlb_status dft_axis(hipStream_t stream, double2 *A, int L, size_t lines, size_t
         HIP_TRY(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     if (pow2)
         hipLaunchKernelGGL(fft_lines_kernel<P>, dim3((unsigned)(lines / P)), dim3(threads), lds, stream, A, L, stride,
-                           inner, inner_stride, outer_stride);
+                           inner, inner_stride, outer_stride, re, im);
     else
         hipLaunchKernelGGL(dft_lines_kernel<P>, dim3((unsigned)(lines / P)), dim3(threads), lds, stream, A, L, stride,
-                           inner, inner_stride, outer_stride);
+                           inner, inner_stride, outer_stride, re, im);
     LAUNCH_CHECK();
     return FMLB_OK;
 }
@@ -285,8 +285,11 @@ fmlb_status dft_axis(hipStream_t stream, double2 *A, int L, size_t lines, size_t
 // Forward DFT of a complex lattice field along every axis of length > 1.
 // The strided axes (y, z) take several adjacent lines per workgroup (as many
 // as divide nx, up to 16, within 4096 elements for the FFT or 148 KB of LDS
-// for the direct sum), so their accesses are contiguous runs.
-fmlb_status dft_field(const Geom &g, hipStream_t stream, double2 *A)
+// for the direct sum), so their accesses are contiguous runs.  With re
+// non-null the field is re + i im and A receives the transform (the lattice
+// must then have an axis of length > 1).
+fmlb_status dft_field(const Geom &g, hipStream_t stream, double2 *A, const double *re = nullptr,
+                      const double *im = nullptr)
 {
     const int dims[3] = {g.nx, g.ny, g.nz};
     for (int ax = 0; ax < 3; ++ax) {
@@ -320,16 +323,17 @@ fmlb_status dft_field(const Geom &g, hipStream_t stream, double2 *A)
         };
         fmlb_status st;
         if (fits(16))
-            st = dft_axis<16>(stream, A, L, lines, stride, (int)inner, inner_stride, outer_stride);
+            st = dft_axis<16>(stream, A, L, lines, stride, (int)inner, inner_stride, outer_stride, re, im);
         else if (fits(8))
-            st = dft_axis<8>(stream, A, L, lines, stride, (int)inner, inner_stride, outer_stride);
+            st = dft_axis<8>(stream, A, L, lines, stride, (int)inner, inner_stride, outer_stride, re, im);
         else if (fits(4))
-            st = dft_axis<4>(stream, A, L, lines, stride, (int)inner, inner_stride, outer_stride);
+            st = dft_axis<4>(stream, A, L, lines, stride, (int)inner, inner_stride, outer_stride, re, im);
         else if (fits(2))
-            st = dft_axis<2>(stream, A, L, lines, stride, (int)inner, inner_stride, outer_stride);
+            st = dft_axis<2>(stream, A, L, lines, stride, (int)inner, inner_stride, outer_stride, re, im);
         else
-            st = dft_axis<1>(stream, A, L, lines, stride, (int)inner, inner_stride, outer_stride);
+            st = dft_axis<1>(stream, A, L, lines, stride, (int)inner, inner_stride, outer_stride, re, im);
         if (st) return st;
+        re = im = nullptr;  // later axes transform A in place
     }
     return FMLB_OK;
 }
@@ -359,9 +363,17 @@ fmlb_status sk_accumulate_impl(const fmlb_params &p, const Geom &g, hipStream_t 
     LAUNCH_CHECK();
     const double inv_n = 1.0 / (double)n;
     for (int pair = 0; pair < sk_pairs<L>(); ++pair) {
-        hipLaunchKernelGGL((sk_field_kernel<L>), gb, tb, 0, stream, mom, Z, g, pair, -p.G);
-        LAUNCH_CHECK();
-        if (fmlb_status st = dft_field(g, stream, Z)) return st;
+        // The density and momentum pairs are two moment fields each: the first
+        // transform reads them directly.  The velocity pairs are built first.
+        const double *re = nullptr, *im = nullptr;
+        if (pair <= D && n > 1) {
+            re = mom + (pair == 0 ? 0 : (size_t)(2 + pair - 1) * n);
+            im = mom + (pair == 0 ? n : (size_t)(2 + D + pair - 1) * n);
+        } else {
+            hipLaunchKernelGGL((sk_field_kernel<L>), gb, tb, 0, stream, mom, Z, g, pair, -p.G);
+            LAUNCH_CHECK();
+        }
+        if (fmlb_status st = dft_field(g, stream, Z, re, im)) return st;
         const int kind = pair == 0 ? 0 : (pair <= D ? 1 : 2);
         hipLaunchKernelGGL(sk_pair_accum_kernel, gb, tb, 0, stream, (const double2 *)Z, acc, g, kind,
                            kind == 0 ? inv_n : inv_n / D);
