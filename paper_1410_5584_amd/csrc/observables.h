@@ -212,8 +212,9 @@ __global__ __launch_bounds__(kRedBlock) void health_kernel(const S *src, double 
 // D + 1 the physical barycentric velocity (v_b,x, v_b,y) and, in 3D, D + 2
 // (v_b,z, 0), with v_b = (j_bar_1 + j_bar_2 + (F_1 + F_2) / 2) / rho_t and
 // the force of Eq. (87) at the same time level.  The populations are pulled
-// once per snapshot (sk_moments_kernel); every pair's field is then built
-// from those moments (sk_field_kernel).
+// once per snapshot (sk_moments_kernel); the first line transform reads the
+// density and momentum pairs straight from those moments, and the velocity
+// pairs' fields are built from them first (sk_field_kernel).
 // ---------------------------------------------------------------------------
 template <class L>
 constexpr int sk_pairs()
