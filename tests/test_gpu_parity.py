@@ -258,8 +258,8 @@ def test_checkpoint_and_split_steps_bitwise(fm):
 
 
 @pytest.mark.parametrize("lattice, shape", [("d2q9", (1, 24, 32)), ("d3q19", (16, 8, 6)), ("d3q19", (5, 16, 12)),
-                                            ("d3q19", (2, 32, 4)), ("d2q9", (1, 3, 2048)), ("d2q9", (1, 2048, 4)),
-                                            ("d2q9", (1, 4, 1000))])
+                                            ("d3q19", (2, 32, 4)), ("d3q19", (4, 128, 64)), ("d2q9", (1, 3, 2048)),
+                                            ("d2q9", (1, 2048, 4)), ("d2q9", (1, 4, 1000))])
 def test_observables_match_oracle(fm, orc, lattice, shape):
     """Moments, global sums, one-snapshot structure factors and mode sums of
     the same FP64 state on both sides (Sec. VI A; Eqs. (80), (86), (87)).  The
@@ -267,7 +267,9 @@ def test_observables_match_oracle(fm, orc, lattice, shape):
     with other lengths (the direct-sum path) on every axis, so the z-axis
     transform, the z components of j and v_b and the D3Q19 mode sums are all
     covered; (2, 32, 4) gives the FFT its shortest lines (z: two points, x:
-    four) and four y lines per workgroup; the D2Q9 lines of 2048 (the longest
+    four) and four y lines per workgroup; (4, 128, 64) lines of 64 (three
+    radix-4 passes) and, sixteen to a workgroup, of 128 (a radix-2 pass
+    first); the D2Q9 lines of 2048 (the longest
     transform, a radix-2 pass before five radix-4 ones; along x one per
     workgroup, along y two per workgroup of 1024 threads with 82 KB of LDS)
     and 1000 sites cover both transform paths at their largest sizes."""
