@@ -712,9 +712,10 @@ struct WideRows {
 // lattice row, so each population is read as contiguous nx-site rows and the
 // x halo is the tile's own periodic image (written into the ring's edge
 // columns, no loads).  The halo is then just the rows y0 - 1 and y0 + T1, one
-// site per thread; their populations are pulled into registers before the
-// collision (the LDS holds only the tile's own rows), which keeps the
-// workgroup's LDS within one CU.  Ordering as in fused_tile_async.
+// site per thread.  With 16-bit storage their populations take the same
+// 16-byte row pulls as the tile's own rows, into a second LDS region
+// (158 KB in all); with FP32 they are pulled into registers, since a second
+// region would not fit the CU's 160 KB.  Ordering as in fused_tile_async.
 //
 // The density ring and the row buffer come in as distinct __restrict__
 // pointers: after inlining, the compiler then knows that the ring's LDS
@@ -724,10 +725,10 @@ struct WideRows {
 template <class L, class S, int T0, int T1>
 __device__ __forceinline__ void fused_tile_rows_body(const StepArgs<L, S> &a, int t0, int t1, int mbeg, int mend,
                                                      typename Storage<S>::Real *__restrict__ ring_p,
-                                                     uint32_t *__restrict__ own_p, uint32_t *__restrict__ tab_p)
+                                                     uint32_t *__restrict__ own_p, uint32_t *__restrict__ hown_p,
+                                                     uint32_t *__restrict__ tab_p)
 {
     using Real = typename Storage<S>::Real;
-    using Raw = uint32_t;
     using A = MarchAxes<L>;
     constexpr int Q = L::Q;
     constexpr bool D3 = A::three_d;
@@ -806,12 +807,47 @@ __device__ __forceinline__ void fused_tile_rows_body(const StepArgs<L, S> &a, in
         });
     }
 
+    // put(j, offset) for every row-pull instruction j of the wave's slice of
+    // lattice row prow
+    auto row_offsets = [&](int prow, auto &&put) {
+        const int x0 = (wave % (T0 / 64)) * 64;
+        const int yc[3] = {wrap(prow, -1, n1), prow, wrap(prow, 1, n1)};  // rows prow - c_y for c_y = +1, 0, -1
+        static_for<NI>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            constexpr int G = W.group_of_instr(j);
+            const int gc = 64 * (j - W.first[G]) + lane;  // chunk within the group
+            // the group's populations occupy consecutive chunk ranges: keep the
+            // last one that starts at or before gc (selects, no branches)
+            int c0 = 0, cb = 0, y = prow;
+            uint32_t pop = 0;
+            static_for<2 * Q>([&](auto pc) {
+                constexpr int sp = decltype(pc)::value / Q, i = decltype(pc)::value % Q;
+                if constexpr (WideRows<L, ES>::group_of(i) == G) {
+                    constexpr int start = W.chunk0[sp * Q + i] - 64 * W.first[G];
+                    const bool here = gc >= start;
+                    c0 = here ? start : c0;
+                    cb = here ? (A::c0(i) > 0 ? -W.EPC : 0) : cb;
+                    y = here ? yc[1 - A::c1(i)] : y;
+                    pop = here ? (uint32_t)(sp * Q + i) * pop_bytes : pop;
+                }
+            });
+            int x = x0 + cb + W.EPC * (gc - c0);
+            x = x < 0 ? x + n0 : (x >= n0 ? x - n0 : x);
+            put(jc, pop + ((uint32_t)x + s1 * (uint32_t)y) * ES);
+        });
+    };
+
     // halo: the two rows y0 - 1 and y0 + T1, one site per thread
     const int hrow = tid / T0, hx = tid % T0;
     const int hh1 = hrow == 0 ? 0 : H1 - 1;
     const int hb = hh1 * H0 + hx + 1;
     const int hp0 = hx;
     const int hp1 = ((t1 * T1 - 1 + (hrow == 0 ? 0 : T1 + 1)) % n1 + n1) % n1;
+    // 16-bit storage pulls the halo rows like the own rows, into hown_p, with
+    // their per-lane offsets in registers (FP32 pulls them into registers:
+    // the LDS of a 256x2 FP32 tile has no room for their rows)
+    uint32_t htab[NI];
+    if constexpr (ES == 2) row_offsets(hp1, [&](auto jc, uint32_t v) { htab[decltype(jc)::value] = v; });
     // ring positions of the periodic x images (columns -1 and T0)
     // (second store: the periodic image, or the same cell again)
     auto put_ring = [&](float *row_plane, int box, int lx, float v) {
@@ -858,6 +894,34 @@ __device__ __forceinline__ void fused_tile_rows_body(const StepArgs<L, S> &a, in
             }
         });
     };
+    // The 16-byte pulls of the halo rows of plane m (16-bit storage),
+    // instructions [jb, je).
+    auto halo_issue = [&](int m, auto jb, auto je) {
+        const uint32_t zo[3] = {(uint32_t)wrapm(m - 1) * sm * ES, (uint32_t)m * sm * ES,
+                                (uint32_t)wrapm(m + 1) * sm * ES};
+        lds_void_t *base = (lds_void_t *)(hown_p + wave * NI * 256);
+        static_for<NI>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            if constexpr (j >= decltype(jb)::value && j < decltype(je)::value) {
+                lds_void_t *dst = (lds_void_t *)((__attribute__((address_space(3))) unsigned char *)base + j * 1024);
+                constexpr int lanes = W.lanes_of_instr(j);
+                if (lanes == 64 || lane < lanes)
+                    __builtin_amdgcn_raw_ptr_buffer_load_lds(rall, dst, 16, htab[j], zo[W.group_of_instr(j)], 0, 0);
+            }
+        });
+    };
+    // Density deviations of this thread's halo site, from the wave's halo chunks.
+    auto halo_read = [&](Real (&r)[2]) {
+        const unsigned short *h = reinterpret_cast<const unsigned short *>(hown_p);
+        Real f[2][Q], j[3];
+        static_for<2 * Q>([&](auto pc) {
+            constexpr int sp = decltype(pc)::value / Q, i = decltype(pc)::value % Q;
+            constexpr int e = W.EPC * W.chunk0[sp * Q + i] + WideRows<L, ES>::shift_of(i);
+            f[sp][i] = DmaWord<S>::decode(h[wave * NI * 512 + e + lane]);
+        });
+#pragma unroll
+        for (int s = 0; s < 2; ++s) moments<L, Real>(f[s], r[s], j);
+    };
     // Read back this thread's 2Q pre-collision populations from the wave's chunks.
     auto wide_read = [&](Real (&f)[2][Q]) {
         static_for<2 * Q>([&](auto pc) {
@@ -875,44 +939,18 @@ __device__ __forceinline__ void fused_tile_rows_body(const StepArgs<L, S> &a, in
     using J0 = std::integral_constant<int, 0>;
     using JE = std::integral_constant<int, (NI + 1) / 2>;
     using JN = std::integral_constant<int, NI>;
+    // 16-bit halo pulls: instructions [0, JH) after the force, [JH, NI) with
+    // the second half of the row pulls (stochastic rounding, with more work
+    // in the stores, issues fewer before the collision)
+    using JH = std::integral_constant<int, Storage<S>::stochastic ? NI / 2 : (NI + 1) / 2>;
 
-    // Register pull of one species.  16-bit words stay raw until they are
-    // read: a widening next to its load, between the scheduling fences
-    // below, would make every load wait for all memory operations in flight
-    // (256x2 BF16: 1.89 -> 0.99 ms per step at 256^3).
-    using HaloWord = std::conditional_t<ES == 4, Real, Raw>;
-    auto pull1 = [&](int s, int q0, int q1, int m, HaloWord (&w)[2][Q]) {
+    // Register pull of one species' halo site (FP32).
+    auto pull1 = [&](int s, int q0, int q1, int m, Real (&w)[2][Q]) {
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            if constexpr (ES == 4)
-                w[s][i] = BufIO<S>::load(rsrc[s], pull_off(q0, q1, m, i), (uint32_t)i * pop_bytes);
-            else
-                w[s][i] = __builtin_amdgcn_raw_buffer_load_b16(rsrc[s], pull_off(q0, q1, m, i), (uint32_t)i * pop_bytes, 0);
-        }
+        for (int i = 0; i < Q; ++i) w[s][i] = BufIO<S>::load(rsrc[s], pull_off(q0, q1, m, i), (uint32_t)i * pop_bytes);
     };
-    // 16-bit halo pulls take the offsets (in sites) of the source planes
-    // m - c_z, c_z = +1, 0, -1, once per plane for both species: wrapping the
-    // plane inside each load's offset (pull1) cost about 45 scalar
-    // instructions per species, and these steps are bound by instruction
-    // issue (256^3: BF16 0.794 -> 0.745 ms, FP16 0.792 -> 0.758).  FP32 keeps
-    // pull1: with the shared offsets it ran 1.012 -> 1.049 ms.
-    auto src_planes = [&](int m, uint32_t (&zq)[3]) {
-        zq[0] = (uint32_t)wrapm(m - 1) * sm;
-        zq[1] = (uint32_t)m * sm;
-        zq[2] = (uint32_t)wrapm(m + 1) * sm;
-    };
-    auto pull1z = [&](int s, int q0, int q1, const uint32_t (&zq)[3], HaloWord (&w)[2][Q]) {
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            const int x = wrap(q0, -A::c0(i), n0);
-            const int y = D3 ? wrap(q1, -A::c1(i), n1) : 0;
-            const uint32_t voff = ((uint32_t)x + s1 * (uint32_t)y + zq[1 - A::cm(i)]) * ES;
-            w[s][i] = __builtin_amdgcn_raw_buffer_load_b16(rsrc[s], voff, (uint32_t)i * pop_bytes, 0);
-        }
-    };
-
-    // Issue schedule of one plane (per thread: 38 row loads into LDS, 38
-    // halo loads into registers, 38 stores).  A wave can have at most 63
+    // Issue schedule of one plane, FP32 (per thread: 38 row loads into LDS,
+    // 38 halo loads into registers, 38 stores).  A wave can have at most 63
     // vector memory operations in flight, and loads and stores share that
     // counter, so issuing all 76 loads at once stalls the wave until the
     // first of them returns, and the wait at the top of the next plane also
@@ -923,7 +961,13 @@ __device__ __forceinline__ void fused_tile_rows_body(const StepArgs<L, S> &a, in
     // first species is collided, ahead of its stores (measured at 256^3
     // FP32: 1.118 -> 1.037 ms per step against issuing all loads together
     // after the force, 1.033 -> 1.018-1.024 with the first rows moved from
-    // after the force to the top; other orders were slower).
+    // after the force to the top; other orders were slower).  16-bit storage
+    // pulls 7 + 7 row chunks per wave instead (own and halo rows): the first
+    // half of the own rows at the top, the first part of the halo rows after
+    // the force, the rest of both once the first species is collided; the
+    // halo rows are read back at the top (256^3 BF16: 0.767 -> 0.702 ms per
+    // step against the register halo, FP16 0.756 -> 0.703; all halo rows at
+    // the top 0.81 ms, all after the force 0.73).
     Real cur[2][Q], rc[2], jc[2][3];
     // Prologue: densities of plane mbeg-1, populations and moments of plane
     // mbeg (register pulls), then the asynchronous pull of plane mbeg+1.
@@ -955,13 +999,11 @@ __device__ __forceinline__ void fused_tile_rows_body(const StepArgs<L, S> &a, in
         }
     }
     wide_issue(wrapm(mbeg + 1), J0{}, JN{});
-    HaloWord hn[2][Q];
-    if constexpr (ES == 4) {
+    Real hn[2][Q];
+    if constexpr (ES == 4)
         pull(hp0, hp1, wrapm(mbeg + 1), hn);
-    } else {
-        pull1(0, hp0, hp1, wrapm(mbeg + 1), hn);
-        pull1(1, hp0, hp1, wrapm(mbeg + 1), hn);
-    }
+    else
+        halo_issue(wrapm(mbeg + 1), J0{}, JN{});
 
 #pragma unroll 1
     for (int m = mbeg; m < mend; ++m) {
@@ -969,12 +1011,12 @@ __device__ __forceinline__ void fused_tile_rows_body(const StepArgs<L, S> &a, in
         __builtin_amdgcn_s_waitcnt(kWaitVm0);
         Real nxt[2][Q], rn[2], jn[2][3];
         wide_read(nxt);
-        // This wave's chunks are read back: its region is free for the
-        // first half of the row pulls of plane m+2.
         __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
         __builtin_amdgcn_sched_barrier(0);
         if (m + 2 <= mend) wide_issue(wrapm(m + 2), J0{}, JE{});
         __builtin_amdgcn_sched_barrier(0);
+        Real hr[2];
+        if constexpr (ES == 2) halo_read(hr);
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
             moments<L, Real>(nxt[s], rn[s], jn[s]);
@@ -983,22 +1025,14 @@ __device__ __forceinline__ void fused_tile_rows_body(const StepArgs<L, S> &a, in
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
             Real r, j[3];
-            if constexpr (ES == 4) {
+            if constexpr (ES == 4)
                 moments<L, Real>(hn[s], r, j);
-            } else {
-                Real h[Q];
-#pragma unroll
-                for (int i = 0; i < Q; ++i) h[i] = DmaWord<S>::decode(hn[s][i]);
-                moments<L, Real>(h, r, j);
-            }
+            else
+                r = hr[s];
             put_ring(ring[slot(m + 1)][s], hb, hx, r);
         }
-        uint32_t zq[3];
         if constexpr (ES == 4) {
             if (m + 2 <= mend) pull1(0, hp0, hp1, wrapm(m + 2), hn);
-        } else {
-            src_planes(wrapm(m + 2), zq);
-            if (m + 2 <= mend) pull1z(0, hp0, hp1, zq, hn);
         }
         // Workgroup barrier for the density ring only: the ring writes are
         // complete once lgkmcnt drains (no row loads are in flight here).
@@ -1013,14 +1047,15 @@ __device__ __forceinline__ void fused_tile_rows_body(const StepArgs<L, S> &a, in
         };
         Real acc[2][3];
         lattice_acceleration<L, Real>(nb, a.ph.negG, acc);
-        // The second species' halo of plane m+2.
+        // The second species' halo of plane m+2 (FP32), the first part of
+        // the halo rows (16-bit).
         const bool more = m + 2 <= mend;
         __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
         __builtin_amdgcn_sched_barrier(0);
         if constexpr (ES == 4) {
             if (more) pull1(1, hp0, hp1, wrapm(m + 2), hn);
         } else {
-            if (more) pull1z(1, hp0, hp1, zq, hn);
+            if (more) halo_issue(wrapm(m + 2), J0{}, JH{});
         }
         __builtin_amdgcn_sched_barrier(0);
         const uint32_t site = (uint32_t)p0 + s1 * (uint32_t)(D3 ? p1 : 0) + sm * (uint32_t)m;
@@ -1029,6 +1064,9 @@ __device__ __forceinline__ void fused_tile_rows_body(const StepArgs<L, S> &a, in
             if (s == 0) {
                 __builtin_amdgcn_sched_barrier(0);
                 if (more) wide_issue(wrapm(m + 2), JE{}, JN{});
+                if constexpr (ES == 2) {
+                    if (more) halo_issue(wrapm(m + 2), JH{}, JN{});
+                }
                 __builtin_amdgcn_sched_barrier(0);
             }
             if (inside) {
@@ -1059,7 +1097,12 @@ __device__ __forceinline__ void fused_tile_rows(const StepArgs<L, S> &a, int t0,
     constexpr int NW = T0 * T1 / 64, NI = WideRows<L, sizeof(S)>().NI;
     __shared__ __attribute__((aligned(16))) uint32_t own[NW * NI * 256];  // 16-byte buffer-to-LDS targets
     __shared__ uint32_t tab[NW * NI * 64];
-    fused_tile_rows_body<L, S, T0, T1>(a, t0, t1, mbeg, mend, &ring[0][0][0], &own[0], &tab[0]);
+    if constexpr (sizeof(S) == 2) {
+        __shared__ __attribute__((aligned(16))) uint32_t hown[NW * NI * 256];  // halo rows, same layout
+        fused_tile_rows_body<L, S, T0, T1>(a, t0, t1, mbeg, mend, &ring[0][0][0], &own[0], &hown[0], &tab[0]);
+    } else {
+        fused_tile_rows_body<L, S, T0, T1>(a, t0, t1, mbeg, mend, &ring[0][0][0], &own[0], nullptr, &tab[0]);
+    }
 }
 
 template <class L, class S, int T0, int T1, bool ASYNC>
