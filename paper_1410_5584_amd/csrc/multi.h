@@ -78,6 +78,11 @@ __device__ __forceinline__ void multi_pull(const S *src, const Geom &g, int x, i
 }
 
 template <class L, class S, int N>
+__device__ __forceinline__ void multi_potential(const MultiPhys<typename Storage<S>::Real> &ph,
+                                                const typename Storage<S>::Real (&f)[N][L::Q],
+                                                typename Storage<S>::Real (&phi)[N]);
+
+template <class L, class S, int N>
 __global__ __launch_bounds__(256) void multi_potential_kernel(MultiArgs<S> a)
 {
     using Real = typename Storage<S>::Real;

@@ -486,6 +486,10 @@ def test_full_size_c3_sampled(fm, orc, storage, u):
     # fewer planes than the three-plane ring: the plane indices wrap onto copies
     ("d3q19", (1, 6, 70), [(1, 0, 0), (64, 4, 1), (64, 8, 3), (128, 4, 2), (0, 0, 0)]),
     ("d3q19", (2, 5, 256), [(1, 0, 0), (256, 2, 1), (256, 2, 2), (128, 4, 5), (0, 0, 0)]),
+    # full-width tiles whose halo rows are their own rows (ny = 2), or whose
+    # second row lies outside and wraps onto the first (ny = 1)
+    ("d3q19", (3, 2, 256), [(1, 0, 0), (256, 2, 1), (256, 2, 3), (0, 0, 0)]),
+    ("d3q19", (4, 1, 256), [(1, 0, 0), (256, 2, 2), (256, 2, 4), (0, 0, 0)]),
     ("d2q9", (1, 2, 64), [(1, 0, 0), (64, 1, 1), (64, 1, 3), (0, 0, 0)]),
     ("d2q9", (1, 1, 300), [(1, 0, 0), (256, 1, 1), (128, 1, 4), (0, 0, 0)]),
 ])
