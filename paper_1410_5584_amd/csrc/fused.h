@@ -808,7 +808,9 @@ __device__ __forceinline__ void fused_tile_rows_body(const StepArgs<L, S> &a, in
     }
 
     // put(j, offset) for every row-pull instruction j of the wave's slice of
-    // lattice row prow
+    // lattice row prow: the same offsets as the table above, for the 16-bit
+    // halo rows (the own rows keep the code above: routed through this lambda
+    // they changed the register allocation of the FP32 kernel)
     auto row_offsets = [&](int prow, auto &&put) {
         const int x0 = (wave % (T0 / 64)) * 64;
         const int yc[3] = {wrap(prow, -1, n1), prow, wrap(prow, 1, n1)};  // rows prow - c_y for c_y = +1, 0, -1
