@@ -484,6 +484,26 @@ constexpr size_t kMaxLdsBytes = 160 * 1024;  // per workgroup (gfx950)
 // sigma is collided, ahead of its stores.  After the first row load of an
 // iteration no LDS read follows until the vmcnt(0) at the top of the next
 // one.  Same helpers in the same order as the two-pass form: the same bits.
+// When species s's row pulls of plane m+2 are issued in the plane loop below:
+// 0 at the top (once the rows of plane m+1 are read back), 1 after the force,
+// 2 + k once species k is collided.  Three or more species: all but the last
+// at the top, the last after the force (256^3: three species 2.09 -> 2.06 ms,
+// four 2.88 -> 2.74 ms); two species: the first after the force, the second
+// after the first species' collision (1.165 ms, against 1.21 with the other
+// rule).
+template <int N>
+constexpr int multi_pull_phase(int s)
+{
+    return N >= 3 ? (s < N - 1 ? 0 : 1) : (s == 0 ? 1 : 2 + (s - 1));
+}
+template <int N>
+constexpr bool multi_phase_used(int ph)
+{
+    for (int s = 0; s < N; ++s)
+        if (multi_pull_phase<N>(s) == ph) return true;
+    return false;
+}
+
 template <class L, int N, int T0, int T1>
 __global__ __launch_bounds__(T0 *T1) void multi_async_kernel(MultiArgs<float> a, int chunk)
 {
@@ -594,6 +614,13 @@ __global__ __launch_bounds__(T0 *T1) void multi_async_kernel(MultiArgs<float> a,
         dma1(s, p0, p1, m, &own[0][0], NT);
         if (tid < NHALO) dma1(s, hp0, hp1, m, &halo[0][0], NHALO);
     };
+    // The pulls of every species whose phase (multi_pull_phase) is ph.
+    auto issue_phase = [&](auto ph, int m) __attribute__((always_inline)) {
+        static_for<N>([&](auto tc) {
+            constexpr int t = decltype(tc)::value;
+            if constexpr (multi_pull_phase<N>(t) == decltype(ph)::value) issue(t, m);
+        });
+    };
     auto read_rows = [&](const Raw *rows, int len, Real (&f)[N][Q]) __attribute__((always_inline)) {
 #pragma unroll
         for (int s = 0; s < N; ++s)
@@ -643,8 +670,16 @@ __global__ __launch_bounds__(T0 *T1) void multi_async_kernel(MultiArgs<float> a,
             read_rows(&halo[0][0], NHALO, h);
             put_phi(m + 1, hb, h);
         }
+        // This wave's rows are read back: the pulls of plane m+2 due at the top.
+        if constexpr (multi_phase_used<N>(0)) {
+            __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
+            __builtin_amdgcn_sched_barrier(0);
+            if (m + 2 <= mend) issue_phase(std::integral_constant<int, 0>{}, wrapm(m + 2));
+            __builtin_amdgcn_sched_barrier(0);
+        }
         // Workgroup barrier for the potential ring only: the ring writes are
-        // complete once lgkmcnt drains (no row loads are in flight here).
+        // complete once lgkmcnt drains (row loads in flight write only this
+        // wave's own rows, which no other wave reads).
         __atomic_signal_fence(__ATOMIC_SEQ_CST);
         __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
         __builtin_amdgcn_s_barrier();
@@ -656,11 +691,12 @@ __global__ __launch_bounds__(T0 *T1) void multi_async_kernel(MultiArgs<float> a,
                 return ring[slot(m + A::cm(i))][s][box_own + A::c1(i) * H0 + A::c0(i)];
             },
             acc);
-        // Every LDS read of this iteration is done: the row loads of plane m+2.
+        // Every LDS read of this iteration is done: the row loads of plane m+2
+        // due after the force.
         const bool more = m + 2 <= mend;
         __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
         __builtin_amdgcn_sched_barrier(0);
-        if (more) issue(0, wrapm(m + 2));
+        if (more) issue_phase(std::integral_constant<int, 1>{}, wrapm(m + 2));
         __builtin_amdgcn_sched_barrier(0);
         const uint32_t site = (uint32_t)p0 + s1 * (uint32_t)(D3 ? p1 : 0) + sm * (uint32_t)m;
         const uint32_t voff = site * 4u;
@@ -672,9 +708,12 @@ __global__ __launch_bounds__(T0 *T1) void multi_async_kernel(MultiArgs<float> a,
             },
             [&](auto sc, auto &fs) __attribute__((always_inline)) {
                 constexpr int s = decltype(sc)::value;
-                if constexpr (s + 1 < N) {
+                // (with three or more species the fences stay even where
+                // nothing is issued: they keep the scheduler from moving work
+                // across the species' stores, about 0.5 %)
+                if constexpr (N >= 3 || multi_phase_used<N>(2 + s)) {
                     __builtin_amdgcn_sched_barrier(0);
-                    if (more) issue(s + 1, wrapm(m + 2));
+                    if (more) issue_phase(std::integral_constant<int, 2 + s>{}, wrapm(m + 2));
                     __builtin_amdgcn_sched_barrier(0);
                 }
                 if (inside) {
