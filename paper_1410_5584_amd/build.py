@@ -24,9 +24,12 @@ FLAGS = [
 ]
 
 # The instruction-level-parallelism scheduler runs the D3Q19 fused steps (and
-# the BF16 D2Q9 one) faster; it slows the D2Q9 FP32 step, the batched and
-# N-species kernels gain nothing from it, so those keep the default.
-SOURCE_FLAGS = {"fused_ilp.hip": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]}
+# the BF16 D2Q9 one) and the N-species steps faster (three species at 256^3:
+# 2.06-2.09 -> 2.005-2.008 ms, four 2.75 -> 2.70, two unchanged); it slows the
+# D2Q9 FP32 step and the batched kernels gain nothing from it, so those keep
+# the default.
+_ILP = ["-mllvm", "-amdgpu-sched-strategy=max-ilp"]
+SOURCE_FLAGS = {"fused_ilp.hip": _ILP, "multi.hip": _ILP}
 
 
 def hipcc() -> str:
