@@ -54,6 +54,9 @@ def test_parity_stochastic_16bit(fm, orc, storage, tol, lattice, shape):
 
 @pytest.mark.parametrize("lattice,shape,tiles", [
     ("d3q19", (7, 5, 256), [(1, 0, 0), (256, 2, 3), (256, 2, 64), (128, 4, 2), (64, 4, 3), (0, 0, 0)]),
+    # full-width tiles whose halo rows are their own rows, or wrap onto them
+    ("d3q19", (3, 2, 256), [(1, 0, 0), (256, 2, 1), (256, 2, 3), (0, 0, 0)]),
+    ("d3q19", (4, 1, 256), [(1, 0, 0), (256, 2, 2), (256, 2, 4), (0, 0, 0)]),
     ("d2q9", (1, 37, 300), [(1, 0, 0), (64, 1, 5), (128, 1, 16), (256, 1, 2)]),
 ])
 @pytest.mark.parametrize("storage", ["bf16", "f16"])
