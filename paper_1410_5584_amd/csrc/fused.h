@@ -36,10 +36,12 @@
 namespace fmlb {
 
 // Raw buffer access per storage type (values are bit patterns on the wire).
-// Stores carry the non-temporal hint (cache-policy bit 1): the populations
-// written now are read only in the next step, so they should not evict the
-// lines the neighbouring tiles are about to re-read for their halo densities
-// (measured on 256^3 D3Q19: 23 % -> 9 % of re-fetched bytes, 4 % faster).
+// Stores carry the non-temporal hint (cache-policy bit 1) by default: the
+// populations written now are read only in the next step, so they should not
+// evict the lines the neighbouring tiles are about to re-read for their halo
+// densities (measured on 256^3 D3Q19: 23 % -> 9 % of re-fetched bytes, 4 %
+// faster).  Lattices whose state fits the last-level cache store without it
+// (launch_fused_shape).
 constexpr int kBufferWord3 = 0x00020000;
 constexpr int kStoreNonTemporal = 2;
 
@@ -52,9 +54,10 @@ struct BufIO<float> {
     {
         return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
     }
+    template <int CPOL = kStoreNonTemporal>
     __device__ static void store(float v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
     {
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, kStoreNonTemporal);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, CPOL);
     }
 };
 
@@ -65,10 +68,11 @@ struct BufIO<__hip_bfloat16> {
         const unsigned short b = __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0);
         return __builtin_bit_cast(float, (uint32_t)b << 16);
     }
+    template <int CPOL = kStoreNonTemporal>
     __device__ static void store(float v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
     {
         const __hip_bfloat16 h = __float2bfloat16(v);
-        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, h), r, voff, soff, kStoreNonTemporal);
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, h), r, voff, soff, CPOL);
     }
 };
 
@@ -79,9 +83,10 @@ struct BufIO<__half> {
         const unsigned short b = __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0);
         return __half2float(__ushort_as_half(b));
     }
+    template <int CPOL = kStoreNonTemporal>
     __device__ static void store(float v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff)
     {
-        __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(__float2half_rn(v)), r, voff, soff, kStoreNonTemporal);
+        __builtin_amdgcn_raw_buffer_store_b16(__half_as_ushort(__float2half_rn(v)), r, voff, soff, CPOL);
     }
 };
 
@@ -93,9 +98,10 @@ struct BufIO<bf16_sr> {
     {
         return BufIO<__hip_bfloat16>::load(r, voff, soff);
     }
+    template <int CPOL = kStoreNonTemporal>
     __device__ static void store(float v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, uint32_t h)
     {
-        __builtin_amdgcn_raw_buffer_store_b16(bf16_bits_sr(v, h), r, voff, soff, kStoreNonTemporal);
+        __builtin_amdgcn_raw_buffer_store_b16(bf16_bits_sr(v, h), r, voff, soff, CPOL);
     }
 };
 
@@ -105,22 +111,24 @@ struct BufIO<f16_sr> {
     {
         return BufIO<__half>::load(r, voff, soff);
     }
+    template <int CPOL = kStoreNonTemporal>
     __device__ static void store(float v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, uint32_t h)
     {
-        __builtin_amdgcn_raw_buffer_store_b16(f16_bits_sr(v, h), r, voff, soff, kStoreNonTemporal);
+        __builtin_amdgcn_raw_buffer_store_b16(f16_bits_sr(v, h), r, voff, soff, CPOL);
     }
 };
 
 // Store population sp_pop (= species * Q + i) of a site after the step with
-// counter `step`: round to nearest, or stochastically for the _sr formats.
-template <class S>
+// counter `step`: round to nearest, or stochastically for the _sr formats;
+// CPOL is the stores' cache policy.
+template <class S, int CPOL = kStoreNonTemporal>
 __device__ __forceinline__ void store_stepped(float v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff,
                                               uint32_t site, uint32_t sp_pop, uint32_t step, uint32_t k0, uint32_t k1)
 {
     if constexpr (Storage<S>::stochastic)
-        BufIO<S>::store(v, r, voff, soff, sr_bits(site, sp_pop, step, k0, k1));
+        BufIO<S>::template store<CPOL>(v, r, voff, soff, sr_bits(site, sp_pop, step, k0, k1));
     else
-        BufIO<S>::store(v, r, voff, soff);
+        BufIO<S>::template store<CPOL>(v, r, voff, soff);
 }
 
 template <class L>
@@ -367,7 +375,7 @@ struct DmaWord<f16_sr> : DmaWord<__half> {
 constexpr int kWaitVm0 = (0x7 << 4) | (0xf << 8);
 constexpr int kWaitLgkm0 = 0xf | (0x7 << 4) | (0x3 << 14);
 
-template <class L, class S, int T0, int T1>
+template <class L, class S, int T0, int T1, int CPOL = kStoreNonTemporal>
 __device__ __forceinline__ void fused_tile_async(const StepArgs<L, S> &a, int t0, int t1, int mbeg, int mend)
 {
     using Real = typename Storage<S>::Real;
@@ -630,7 +638,7 @@ __device__ __forceinline__ void fused_tile_async(const StepArgs<L, S> &a, int t0
 #pragma unroll
                 for (int i = 0; i < Q; ++i) {
                     Real v = fs[i];
-                    store_stepped<S>(v, rdst[s], voff, (uint32_t)i * popb_v, site, (uint32_t)(s * Q + i),
+                    store_stepped<S, CPOL>(v, rdst[s], voff, (uint32_t)i * popb_v, site, (uint32_t)(s * Q + i),
                                      a.step_lo, a.ph.key0, a.ph.key1);
                 }
             }
@@ -1107,7 +1115,7 @@ __device__ __forceinline__ void fused_tile_rows(const StepArgs<L, S> &a, int t0,
     }
 }
 
-template <class L, class S, int T0, int T1, bool ASYNC>
+template <class L, class S, int T0, int T1, bool ASYNC, int CPOL = kStoreNonTemporal>
 __global__ __launch_bounds__(T0 *T1) void fused_step_kernel(StepArgs<L, S> a, int chunk)
 {
     constexpr bool D3 = L::D == 3;
@@ -1122,7 +1130,7 @@ __global__ __launch_bounds__(T0 *T1) void fused_step_kernel(StepArgs<L, S> a, in
     if constexpr (L::D == 3 && T0 == 256)
         fused_tile_rows<L, S, T0, T1>(a, t0, t1, mbeg, mend);
     else if constexpr (ASYNC)
-        fused_tile_async<L, S, T0, T1>(a, t0, t1, mbeg, mend);
+        fused_tile_async<L, S, T0, T1, CPOL>(a, t0, t1, mbeg, mend);
     else
         fused_tile<L, S, T0, T1>(a, t0, t1, mbeg, mend);
 }
@@ -1206,12 +1214,27 @@ bool fused_supported(const Geom &g, int tile_x, int tile_y, int march)
 #define FMLB_FUSED_ASYNC 1
 #endif
 
+// Both state buffers (read and written each step) up to this size stay in
+// MI355X's 256 MB last-level cache from one step to the next if the stores
+// keep it: the tiled kernel then stores without the non-temporal hint (D2Q9
+// 1024^2, 151 MB: 0.0364 -> 0.0317 ms per step; D3Q19 64^3, 80 MB: 0.0265 ->
+// 0.0258; D3Q19 128^3, 637 MB, would lose 2 % without the hint).
+constexpr double kCacheResidentBytes = 192.0 * 1024 * 1024;
+
 template <class L, class S, int T0, int T1, bool ASYNC = FMLB_FUSED_ASYNC>
 hipError_t launch_fused_shape(const StepArgs<L, S> &a, int chunk, hipStream_t stream)
 {
     const int n0 = a.g.nx, n1 = L::D == 3 ? a.g.ny : 1, nm = L::D == 3 ? a.g.nz : a.g.ny;
     const unsigned nblk = (unsigned)((n0 + T0 - 1) / T0) * (unsigned)((n1 + T1 - 1) / T1) *
                           (unsigned)((nm + chunk - 1) / chunk);
+    if constexpr (ASYNC && !(L::D == 3 && T0 == 256)) {
+        const double state = 2.0 * 2 * L::Q * (double)a.g.pitch * sizeof(S);
+        if (state <= kCacheResidentBytes) {
+            hipLaunchKernelGGL((fused_step_kernel<L, S, T0, T1, ASYNC, 0>), dim3(nblk), dim3(T0 * T1), 0, stream, a,
+                               chunk);
+            return hipGetLastError();
+        }
+    }
     hipLaunchKernelGGL((fused_step_kernel<L, S, T0, T1, ASYNC>), dim3(nblk), dim3(T0 * T1), 0, stream, a, chunk);
     return hipGetLastError();
 }
